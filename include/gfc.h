@@ -1,0 +1,211 @@
+/*
+ * gfc.h -- C ABI of the MI355X (gfx950) renderer for the hybrid Fourier-real
+ * mixture-of-Gaussians galaxy-PSF convolution of Lang (2020),
+ * "A hybrid Fourier-Real Gaussian Mixture method for fast galaxy-PSF
+ * convolution", arXiv:2012.15797.
+ *
+ * Method (Section 2, steps 1-8): the FFT of the pixelized PSF (cached per PSF
+ * and stamp size) is multiplied by the analytic Fourier transform of the
+ * affine-transformed, sub-pixel-shifted Gaussian-mixture galaxy evaluated on
+ * the FFT frequency grid, and inverse-FFT'd; mixture components that would
+ * alias (wrap around) are instead convolved analytically with a single
+ * Gaussian approximation of the PSF and evaluated in pixel space.
+ *
+ * Conventions used by every call:
+ *   - All functions return gfc_status (0 = OK, < 0 = error).  No C++
+ *     exception crosses the ABI.  On error a message is available from
+ *     gfc_last_error() on the calling thread.
+ *   - "device" pointers are HIP device allocations on the context's device;
+ *     "host" pointers are ordinary host memory.  Host inputs are copied
+ *     before the call returns; the caller keeps ownership of everything it
+ *     passes.  Device buffers passed to an asynchronous call must stay alive
+ *     until the stream has completed it.
+ *   - Pixel (row r, column c) of a stamp has its centre at (x = c, y = r),
+ *     0-based.  Stamps are float32, row-major [n][W][W].
+ *   - A pixelized PSF of S_y x S_x pixels (both even) has its centre at pixel
+ *     (S_y/2, S_x/2); that pixel is moved to frequency-grid index 0 and the
+ *     grid is folded periodically modulo W (zero padding when W >= S).
+ *   - Mixture variances are isotropic, in units of r_e^2 (Section 2 step 3:
+ *     V = v I); amplitudes are used as given (never renormalised).
+ *   - Step 4 routing: n_i = (W/2) / sqrt(tr C_i); component i is evaluated in
+ *     Fourier space with weight w_i = 1 when n_i >= 4, in real space when
+ *     n_i <= 3, and with both in between, w_i = smoothstep(n_i - 3).
+ *   - At the Nyquist index of each axis the galaxy transform is the mean of
+ *     its values at frequencies +1/2 and -1/2 (the product with the PSF
+ *     spectrum is then exactly Hermitian and the inverse FFT exactly real).
+ *   - Real-space components are point-sampled at pixel centres, not wrapped.
+ */
+#ifndef GFC_H_
+#define GFC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GFC_OK = 0,
+  GFC_EINVAL = -1,       /* bad argument (NULL handle, unsupported size, ...) */
+  GFC_EUNSUPPORTED = -2, /* valid request this build does not implement */
+  GFC_ENOMEM = -3,       /* device or host allocation failed */
+  GFC_EDEVICE = -4,      /* a HIP runtime call failed; see gfc_last_error() */
+  GFC_EBUSY = -5,        /* object in use (e.g. server still has requests) */
+  GFC_EREJECTED = -6,    /* serving: request can never fit the memory budget */
+  GFC_ETIMEOUT = -7      /* serving: wait timed out */
+} gfc_status;
+
+typedef struct gfc_ctx gfc_ctx;
+typedef struct gfc_psf gfc_psf;
+typedef struct gfc_mix gfc_mix;
+typedef struct gfc_server gfc_server;
+
+/* Largest number of mixture components per table. */
+#define GFC_KMAX 16
+
+/* Per-call flags (Section 2 step 4 routing overrides). */
+enum {
+  GFC_FORCE_FOURIER = 1, /* every component in Fourier space (w_i = 1) */
+  GFC_FORCE_REAL = 2,    /* every component in real space (w_i = 0) */
+  GFC_RAMP_LINEAR = 4    /* linear ramp w_i = n_i - 3 instead of smoothstep */
+};
+
+const char* gfc_status_str(gfc_status s);
+/* Message of the last failing call on this thread ("" if none). */
+const char* gfc_last_error(void);
+
+/* Supported stamp sizes W: 16, 32, 64, 128, 256. Returns 1 if supported. */
+int gfc_stamp_size_supported(int W);
+
+/* ---------------------------------------------------------------- context */
+/* Binds to HIP device `hip_device`.  Owns the PSF-FT caches of the PSFs
+ * created on it and a device counter of invalid galaxies. */
+gfc_status gfc_ctx_create(int hip_device, gfc_ctx** out);
+/* Synchronises the device, then frees the context.  All PSFs, mixtures and
+ * servers created on it must have been destroyed first (GFC_EBUSY if not). */
+gfc_status gfc_ctx_destroy(gfc_ctx* ctx);
+/* Number of galaxies rendered with invalid parameters (|e| >= 1, r_e <= 0,
+ * a non-finite value, |x| or |y| > 2^23, mix_id out of range) since the
+ * context was created.  Synchronises the device. */
+gfc_status gfc_ctx_invalid_count(gfc_ctx* ctx, uint64_t* n_invalid);
+
+/* ------------------------------------------------------------------- PSF */
+/* Steps 1-2.  pix: host, S_y*S_x row-major pixel values (copied).  S_y, S_x
+ * even, 2..1024.  gauss: host pointer to {mu_x, mu_y, c_xx, c_xy, c_yy, amp}
+ * (float64) describing the single-Gaussian PSF approximation used by
+ * real-space components (Step 8), mu relative to the centre pixel; NULL
+ * selects moment matching about the centre pixel with amp = sum of pixels.
+ * The covariance must be positive semi-definite (else GFC_EINVAL). */
+gfc_status gfc_psf_create(gfc_ctx* ctx, const float* pix, int S_y, int S_x,
+                          const double* gauss, gfc_psf** out);
+gfc_status gfc_psf_create_f64(gfc_ctx* ctx, const double* pix, int S_y, int S_x,
+                              const double* gauss, gfc_psf** out);
+/* Writes the Gaussian approximation in use to gauss_out[6] (host). */
+gfc_status gfc_psf_gauss(const gfc_psf* psf, double* gauss_out);
+/* Fills the PSF-FT cache for stamp size W on `hip_stream` (the render calls
+ * do this lazily on first use of a size).  Cold path: one separable DFT of
+ * the PSF in float64, stored as complex float32. */
+gfc_status gfc_psf_prepare(gfc_psf* psf, int W, void* hip_stream);
+/* Copies the cached PSF spectrum for size W into spec_out (device,
+ * [W][W/2+1] interleaved complex float32, natural order: element
+ * (k_y, k_x) = sum_{r,c} P[r][c] exp(-2 pi i (k_x (c - S_x/2) + k_y (r - S_y/2)) / W)).
+ * Fills the cache first if needed.  Asynchronous on hip_stream. */
+gfc_status gfc_psf_spectrum(gfc_psf* psf, int W, float* spec_out, void* hip_stream);
+/* Synchronises the context's device, then frees the PSF and its caches. */
+gfc_status gfc_psf_destroy(gfc_psf* psf);
+
+/* ------------------------------------------------------------- mixtures */
+/* n_tables tables; table t has K[t] (1..GFC_KMAX) components.  amp, var:
+ * host, [n_tables][GFC_KMAX] float32 row-major (entries past K[t] ignored);
+ * var > 0 in r_e^2 units.  Copied to the device. */
+gfc_status gfc_mix_create(gfc_ctx* ctx, int n_tables, const int* K, const float* amp,
+                          const float* var, gfc_mix** out);
+/* Device pointers to the table arrays (amp, var: [n_tables][GFC_KMAX]);
+ * writes through amp_dev change the amplitudes used by later calls. */
+gfc_status gfc_mix_device_tables(gfc_mix* mix, float** amp_dev, float** var_dev);
+gfc_status gfc_mix_destroy(gfc_mix* mix);
+
+/* --------------------------------------------------------------- render */
+/* Galaxy parameters, structure of arrays, device pointers of length n. */
+typedef struct {
+  const float* x;        /* centre, pixels */
+  const float* y;
+  const float* flux;     /* total flux F (rendered flux is F * sum_i A_i) */
+  const float* r_e;      /* effective radius: pixels when cd == NULL */
+  const float* e1;       /* ellipticity components, |e| < 1 */
+  const float* e2;
+  const int32_t* mix_id; /* device, table index per galaxy, or NULL (= 0) */
+  const float* cd;       /* host, 4 floats {CD11, CD12, CD21, CD22} of the
+                            local WCS matrix (pixel -> world), or NULL for the
+                            identity; A = CD^{-1} E (Section 2 step 3) */
+} gfc_galaxies;
+
+/* Steps 3-8 for n galaxies into stamps of size W, asynchronously on
+ * hip_stream.  out: device, n*W*W float32 [n][W][W].  Galaxies with invalid
+ * parameters get an all-NaN stamp and increment the invalid counter; the
+ * call itself does not synchronise.  n == 0 is a no-op. */
+gfc_status gfc_render_stamps(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix* mix,
+                             const gfc_galaxies* gal, int64_t n, int W, unsigned flags,
+                             float* out, void* hip_stream);
+
+/* Adjoint of gfc_render_stamps.  grad_out: device [n][W][W], the upstream
+ * gradient dL/dI.  grad_params: device [n][6] float32 receiving
+ * dL/d(x, y, flux, log r_e, e1, e2) (overwritten), or NULL.  grad_amp:
+ * device [n_tables][GFC_KMAX] float32 to which dL/dA (summed over the
+ * galaxies using each table) is ADDED in a fixed order (deterministic), or
+ * NULL.  At e = 0 the derivative w.r.t. (e1, e2) is taken as 0 (the profile
+ * has a cone there).  workspace: device scratch of at least
+ * gfc_backward_workspace_bytes(n) bytes, or NULL to let the library
+ * allocate it per call.  Asynchronous on hip_stream. */
+size_t gfc_backward_workspace_bytes(int64_t n);
+gfc_status gfc_render_stamps_backward(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix* mix,
+                                      const gfc_galaxies* gal, int64_t n, int W,
+                                      unsigned flags, const float* grad_out,
+                                      float* grad_params, float* grad_amp,
+                                      void* workspace, void* hip_stream);
+
+/* -------------------------------------------------------------- serving */
+/* Continuous batching.  A request carries HOST parameter arrays (copied at
+ * submit).  Its output stamps live in a library-owned device buffer, charged
+ * to the server's memory budget until released. */
+typedef struct {
+  gfc_psf* psf;
+  const gfc_mix* mix;
+  int W;
+  int n;
+  unsigned flags;
+  const float *x, *y, *flux, *r_e, *e1, *e2; /* host, length n */
+  const int32_t* mix_id;                      /* host or NULL */
+} gfc_request;
+
+/* mem_budget_bytes: device bytes the server may hold for admitted requests
+ * (outputs + parameters); max_batch_stamps: most stamps fused into one
+ * launch; n_streams: concurrent launch streams (1..8). */
+gfc_status gfc_server_create(gfc_ctx* ctx, size_t mem_budget_bytes, int n_streams,
+                             int64_t max_batch_stamps, gfc_server** out);
+/* Queues a request; returns at once with a ticket.  GFC_EREJECTED if the
+ * request alone exceeds the budget, GFC_EINVAL for a malformed request. */
+gfc_status gfc_server_submit(gfc_server* srv, const gfc_request* req, uint64_t* ticket);
+/* done = 1 once the stamps are complete in device memory; out_dev then
+ * points at [n][W][W] float32 (valid until release).  status_out (may be
+ * NULL) receives the request's own status. */
+gfc_status gfc_server_poll(gfc_server* srv, uint64_t ticket, int* done, const float** out_dev,
+                           gfc_status* status_out);
+/* Blocks until the request completes or timeout_ms passes (< 0: forever). */
+gfc_status gfc_server_wait(gfc_server* srv, uint64_t ticket, int timeout_ms,
+                           const float** out_dev);
+/* Returns the request's device memory to the budget. */
+gfc_status gfc_server_release(gfc_server* srv, uint64_t ticket);
+/* Latency (submit -> completion) percentiles over completed requests, and
+ * stamps completed per second of server lifetime; also launches issued. */
+gfc_status gfc_server_stats(gfc_server* srv, double* p50_ms, double* p99_ms, double* max_ms,
+                            double* stamps_per_s, uint64_t* n_launches, uint64_t* n_done);
+/* Drains every queued request, then frees the server. */
+gfc_status gfc_server_destroy(gfc_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GFC_H_ */

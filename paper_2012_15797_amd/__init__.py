@@ -1,0 +1,26 @@
+"""MI355X (gfx950) renderer for the hybrid Fourier-real mixture-of-Gaussians
+galaxy-PSF convolution (Lang 2020, arXiv:2012.15797).
+
+The computation lives in libgfc.so (HIP kernels behind the C ABI of
+include/gfc.h); this package only marshals arguments to it, with torch
+supplying device memory and streams.  There is no CPU fallback: when the
+library is missing, loading it raises.
+"""
+
+from ._lib import (  # noqa: F401
+    GFC_FORCE_FOURIER,
+    GFC_FORCE_REAL,
+    GFC_KMAX,
+    GFC_RAMP_LINEAR,
+    GfcError,
+    LIB_PATH,
+    lib,
+)
+from .api import (  # noqa: F401
+    Context,
+    Mixture,
+    Psf,
+    gfc_backward_workspace_bytes,
+    gfc_render_stamps,
+    gfc_render_stamps_backward,
+)

@@ -1,0 +1,116 @@
+// Device-side shared definitions of the renderer: kernel argument blocks and
+// the per-galaxy shape algebra (Section 2, steps 3 and 4).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fft_reg.hpp"
+
+namespace gfc {
+
+constexpr int kKmax = 16;
+// -2 pi^2 log2(e): the Gaussian transform exp(-2 pi^2 q) written as exp2(kQ q).
+constexpr float kQ = -0x1.c7a47ep+4f;
+// -log2(e) / 2: a real-space Gaussian exp(-u^T S^-1 u / 2) as exp2(kHalfLog2e q).
+constexpr float kHalfLog2e = -0x1.715476p-1f;
+constexpr float kInv2Pi = 0x1.45f306p-3f;
+
+// Galaxy parameters and everything a render launch needs.
+struct RenderArgs {
+  const float* x;
+  const float* y;
+  const float* flux;
+  const float* r_e;
+  const float* e1;
+  const float* e2;
+  const int32_t* mix_id;   // may be null (table 0)
+  const float* amp;        // [n_tables][kKmax]
+  const float* var;        // [n_tables][kKmax]
+  const int32_t* K;        // [n_tables]
+  int n_tables;
+  int kmax;                // max K over the tables
+  float cdinv[4];          // CD^{-1}, row-major (identity by default)
+  float pg[6];             // PSF Gaussian: mu_x, mu_y, c_xx, c_xy, c_yy, amp
+  const float2* psf_main;  // PSF spectrum, lane-permuted columns 0..W/2-1
+  const float2* psf_nyq;   // PSF spectrum, Nyquist column k_x = W/2, [W]
+  float* out;              // [n][W][W]
+  int64_t n;
+  unsigned flags;
+  unsigned long long* invalid;  // device counter of invalid galaxies
+};
+
+enum : unsigned { kForceFourier = 1u, kForceReal = 2u, kRampLinear = 4u };
+
+// Per-galaxy state shared by every step.
+struct Galaxy {
+  float x0, y0, flux;
+  float fx, fy;      // fractional centre (in [0, 1))
+  int nx, ny;        // integer centre modulo W
+  float b11, b12, b22;  // pixel-space covariance per unit mixture variance
+  int table, K;
+  bool ok;
+};
+
+__device__ __forceinline__ bool finitef(float v) { return __builtin_isfinite(v); }
+
+// Step 3: C_i = v_i B with B = A A^T, A = CD^{-1} E.  With c^2, s^2 and cs of
+// the position angle written through e1, e2 (Appendix A), E E^T is
+// r_e^2/(1+e)^2 [[1+e^2-2e1, 2e2], [2e2, 1+e^2+2e1]] -- no trigonometry.
+template <int W>
+__device__ __forceinline__ Galaxy load_galaxy(const RenderArgs& p, int64_t g) {
+  Galaxy G;
+  G.x0 = p.x[g];
+  G.y0 = p.y[g];
+  G.flux = p.flux[g];
+  const float re = p.r_e[g], e1 = p.e1[g], e2 = p.e2[g];
+  G.table = p.mix_id ? p.mix_id[g] : 0;
+  const float esq = e1 * e1 + e2 * e2;
+  G.ok = finitef(G.x0) && finitef(G.y0) && finitef(G.flux) && finitef(re) && finitef(e1) &&
+         finitef(e2) && re > 0.f && esq < 1.f && fabsf(G.x0) <= 8388608.f &&
+         fabsf(G.y0) <= 8388608.f && G.table >= 0 && G.table < p.n_tables;
+  if (!G.ok) G.table = 0;
+  G.K = p.K[G.table];
+  const float fxf = floorf(G.x0), fyf = floorf(G.y0);
+  G.fx = G.ok ? G.x0 - fxf : 0.f;
+  G.fy = G.ok ? G.y0 - fyf : 0.f;
+  G.nx = G.ok ? ((int)(fxf - (float)W * floorf(fxf * (1.f / W)))) & (W - 1) : 0;
+  G.ny = G.ok ? ((int)(fyf - (float)W * floorf(fyf * (1.f / W)))) & (W - 1) : 0;
+  const float e = sqrtf(esq);
+  const float s = (re * re) / ((1.f + e) * (1.f + e));
+  const float c11 = s * (1.f + esq - 2.f * e1);
+  const float c12 = s * (2.f * e2);
+  const float c22 = s * (1.f + esq + 2.f * e1);
+  // B = M C M^T with M = CD^{-1}
+  const float m00 = p.cdinv[0], m01 = p.cdinv[1], m10 = p.cdinv[2], m11 = p.cdinv[3];
+  const float p00 = fmaf(m00, c11, m01 * c12), p01 = fmaf(m00, c12, m01 * c22);
+  const float p10 = fmaf(m10, c11, m11 * c12), p11 = fmaf(m10, c12, m11 * c22);
+  G.b11 = fmaf(p00, m00, p01 * m01);
+  G.b12 = fmaf(p00, m10, p01 * m11);
+  G.b22 = fmaf(p10, m10, p11 * m11);
+  return G;
+}
+
+// Step 4: Fourier weight of a component whose covariance trace is `tr`.
+template <int W>
+__device__ __forceinline__ float route_weight(float tr, unsigned flags) {
+  if (flags & kForceFourier) return 1.f;
+  if (flags & kForceReal) return 0.f;
+  const float n = (0.5f * (float)W) / sqrtf(tr);
+  const float t = fminf(fmaxf(n - 3.f, 0.f), 1.f);
+  if (flags & kRampLinear) return t;
+  return t * t * (3.f - 2.f * t);
+}
+
+// d w / d n of route_weight (zero outside the ramp).
+template <int W>
+__device__ __forceinline__ float route_slope(float n, unsigned flags) {
+  if (flags & (kForceFourier | kForceReal)) return 0.f;
+  if (!(n > 3.f && n < 4.f)) return 0.f;
+  const float t = n - 3.f;
+  if (flags & kRampLinear) return 1.f;
+  return 6.f * t * (1.f - t);
+}
+
+}  // namespace gfc

@@ -1,0 +1,71 @@
+// Internal host-side definitions shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <map>
+#include <mutex>
+#include <string>
+
+#include "gfc.h"
+#include "gfc_device.hpp"
+
+struct gfc_ctx {
+  int device = 0;
+  unsigned long long* d_invalid = nullptr;  // device counter of invalid galaxies
+  std::atomic<int> n_objects{0};            // PSFs, mixtures and servers alive
+};
+
+namespace gfc {
+// Cached PSF spectrum for one stamp size W: columns 0..W/2-1 in the order
+// the render kernels' lanes read them, then the Nyquist column.
+struct PsfSpectrum {
+  int W = 0;
+  float2* main_cols = nullptr;  // [W/2][W] (one allocation with nyq_col)
+  float2* nyq_col = nullptr;    // [W]
+};
+}  // namespace gfc
+
+struct gfc_psf {
+  gfc_ctx* ctx = nullptr;
+  int Sy = 0, Sx = 0;
+  double* d_pix = nullptr;  // device, float64 [Sy][Sx]
+  double gauss[6] = {0, 0, 0, 0, 0, 0};
+  std::mutex mu;
+  std::map<int, gfc::PsfSpectrum> cache;
+};
+
+struct gfc_mix {
+  gfc_ctx* ctx = nullptr;
+  int n_tables = 0;
+  int kmax = 0;
+  float* d_amp = nullptr;  // [n_tables][GFC_KMAX]
+  float* d_var = nullptr;
+  int32_t* d_K = nullptr;
+};
+
+namespace gfc {
+
+gfc_status fail(gfc_status s, const std::string& msg);
+gfc_status hip_fail(hipError_t e, const char* what);
+bool stamp_size_ok(int W);
+
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int dev);
+  ~DeviceGuard();
+  DeviceGuard(const DeviceGuard&) = delete;
+  DeviceGuard& operator=(const DeviceGuard&) = delete;
+
+ private:
+  int prev_ = -1;
+};
+
+gfc_status psf_cache(gfc_psf* psf, int W, hipStream_t stream, const PsfSpectrum** out);
+gfc_status fill_render_args(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix* mix, const gfc_galaxies* gal,
+                            int64_t n, int W, unsigned flags, RenderArgs* a);
+// Launches the forward kernels for stamp size W (arguments already validated).
+gfc_status render_launch(const RenderArgs& a, int W, hipStream_t stream);
+
+}  // namespace gfc

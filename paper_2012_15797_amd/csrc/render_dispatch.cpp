@@ -1,0 +1,21 @@
+// Stamp-size dispatch of the forward render.
+#include "gfc_internal.hpp"
+#include "gfc_launch.hpp"
+
+namespace gfc {
+
+gfc_status render_launch(const RenderArgs& a, int W, hipStream_t stream) {
+  hipError_t e = hipErrorInvalidValue;
+  switch (W) {
+    case 16: e = launch_render_small<16>(a, stream); break;
+    case 32: e = launch_render_small<32>(a, stream); break;
+    case 64: e = launch_render_small<64>(a, stream); break;
+    case 128: e = launch_render_small<128>(a, stream); break;
+    case 256: return fail(GFC_EUNSUPPORTED, "W = 256 not built yet");
+    default: return fail(GFC_EINVAL, "unsupported stamp size");
+  }
+  if (e != hipSuccess) return hip_fail(e, "render launch");
+  return GFC_OK;
+}
+
+}  // namespace gfc

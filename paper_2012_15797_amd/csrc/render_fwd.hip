@@ -1,0 +1,266 @@
+// Forward render kernel for stamp sizes W = 16, 32, 64, 128 (Lang 2020,
+// Section 2, steps 3-8), one fused kernel per launch.
+//
+// A stamp is handled by W lanes (W < 64: 64/W stamps per wavefront; W = 128:
+// two wavefronts).  The half spectrum (W/2 + 1 columns) never leaves the chip:
+//
+//  column phase  lane (c, h), c = 0..W/2-1, h = 0..1, owns column k_x = c and
+//                rows k_y = 2m + h.  It evaluates the mixture transform
+//                (steps 5-6) on those bins, multiplies by the fractional-shift
+//                phase, the flux and the cached PSF spectrum (step 7a), and
+//                runs a W/2-point inverse FFT in registers (the even/odd half
+//                of the length-W column transform).  Column k_x = W/2 is
+//                packed into column 0 as its imaginary part: both columns
+//                transform to real vectors because the product is Hermitian.
+//  transpose     through LDS; the last radix-2 stage of the column transform
+//                is applied while reading back.
+//  row phase     lane y owns row y and runs the length-W complex-to-real
+//                inverse transform as a W/2-point complex FFT in registers.
+//  store         rows go through LDS with the integer part of the centre
+//                applied as a cyclic roll, then real-space components
+//                (step 8) are added and stamps are written coalesced.
+#include "gfc_device.hpp"
+#include "gfc_launch.hpp"
+
+namespace gfc {
+
+template <int W>
+struct SmallCfg {
+  static constexpr int M = W / 2;                // values per lane in the column phase
+  static constexpr int BLOCK = W < 64 ? 64 : W;  // threads per workgroup
+  static constexpr int SPB = BLOCK / W;          // stamps per workgroup
+  static constexpr int T1S = W + 1;              // float2 per LDS row (padding kills bank conflicts)
+  static constexpr int T1N = M * T1S;            // float2 per stamp; also W x (W+1) floats
+  static constexpr int CH = W < 32 ? W : 32;     // output rows per chunk
+};
+
+template <int W>
+__global__ void __launch_bounds__(SmallCfg<W>::BLOCK)
+render_small_kernel(RenderArgs p) {
+  using C = SmallCfg<W>;
+  constexpr int M = C::M;
+  constexpr int T1S = C::T1S;
+  __shared__ float2 s_t1[C::SPB][C::T1N];
+  __shared__ float2 s_py[C::SPB][W + 2];
+  __shared__ float2 s_nyq[C::SPB][W];
+
+  const int l = threadIdx.x % W;
+  const int slot = threadIdx.x / W;
+  const int64_t stamp = (int64_t)blockIdx.x * C::SPB + slot;
+  const bool live = stamp < p.n;
+  const Galaxy G = load_galaxy<W>(p, live ? stamp : p.n - 1);
+  const float* amp = p.amp + G.table * kKmax;
+  const float* var = p.var + G.table * kKmax;
+  const int kloop = (C::SPB == 1) ? G.K : p.kmax;
+  const float trB = G.b11 + G.b22;
+
+  // ---------------------------------------------------------------- column phase
+  const int c = l >> 1, h = l & 1;
+  const float nu = (float)c * (1.f / W);
+  const float hW = (float)h * (1.f / W);
+  // exponent per unit mixture variance: kQ (b11 nu^2 + 2 b12 nu om + b22 om^2)
+  const float g0 = kQ * G.b11 * nu * nu;
+  const float g1 = 2.f * kQ * G.b12 * nu;
+  const float g2 = kQ * G.b22;
+  float qv[M + 1];
+  static_for<0, M>([&](auto mm) {
+    constexpr int m = decltype(mm)::value;
+    float om;
+    if constexpr (2 * m < W / 2) om = (float)(2 * m) * (1.f / W) + hW;
+    else if constexpr (2 * m == W / 2) om = h ? (float)(W / 2 + 1 - W) * (1.f / W) : 0.5f;
+    else om = (float)(2 * m - W) * (1.f / W) + hW;
+    qv[m] = fmaf(om, fmaf(g2, om, g1), g0);
+  });
+  qv[M] = fmaf(-0.5f, fmaf(g2, -0.5f, g1), g0);  // Nyquist row, omega = -1/2
+
+  // Nyquist column k_x = W/2: lane l takes row k_y = l at nu = +1/2 and -1/2,
+  // and the omega = -1/2 twins of the corner bin.
+  const float omN = (l < W / 2) ? (float)l * (1.f / W) : (l == W / 2 ? 0.5f : (float)(l - W) * (1.f / W));
+  const float qa = kQ * G.b11 * 0.25f, qb = kQ * G.b12, qd = kQ * G.b22;
+  float qn[4];
+  qn[0] = fmaf(omN, fmaf(qd, omN, qb), qa);      // (+1/2, omN)
+  qn[1] = fmaf(omN, fmaf(qd, omN, -qb), qa);     // (-1/2, omN)
+  qn[2] = fmaf(-0.5f, fmaf(qd, -0.5f, qb), qa);  // (+1/2, -1/2)
+  qn[3] = fmaf(-0.5f, fmaf(qd, -0.5f, -qb), qa); // (-1/2, -1/2)
+
+  float S[M + 1];
+  float SN[4] = {0.f, 0.f, 0.f, 0.f};
+  static_for<0, M + 1>([&](auto mm) { S[decltype(mm)::value] = 0.f; });
+  for (int k = 0; k < kloop; ++k) {
+    const float v = var[k];
+    const float A = (k < G.K) ? amp[k] : 0.f;
+    const float wa = route_weight<W>(v * trB, p.flags) * A;
+    if (wa == 0.f) continue;
+    static_for<0, M + 1>([&](auto mm) {
+      constexpr int m = decltype(mm)::value;
+      S[m] = fmaf(wa, __builtin_amdgcn_exp2f(v * qv[m]), S[m]);
+    });
+    static_for<0, 4>([&](auto jj) {
+      constexpr int j = decltype(jj)::value;
+      SN[j] = fmaf(wa, __builtin_amdgcn_exp2f(v * qn[j]), SN[j]);
+    });
+  }
+
+  // Fractional-shift phases (shift theorem): exp(-2 pi i (fx nu + fy om)).
+  float sx, cx;
+  sincospif(-2.f * G.fx * nu, &sx, &cx);
+  const float fs = G.flux * (1.f / ((float)W * (float)W));
+  const float2 pxF = make_float2(fs * cx, fs * sx);
+  float sy, cy;
+  sincospif(-2.f * G.fy * omN, &sy, &cy);
+  float sym, cym;
+  sincospif(G.fy, &sym, &cym);  // omega = -1/2
+  s_py[slot][l] = make_float2(cy, sy);
+  if (l == 0) s_py[slot][W] = make_float2(cym, sym);
+  {
+    float sxh, cxh;
+    sincospif(-G.fx, &sxh, &cxh);  // nu = +1/2
+    const float2 eM = make_float2(cxh, sxh), eP = make_float2(cxh, -sxh);
+    const bool corner = (l == W / 2);
+    const float2 pyA = corner ? make_float2(0.5f * cy, 0.5f * sy) : make_float2(cy, sy);
+    const float2 pyB = corner ? make_float2(0.5f * cym, 0.5f * sym) : make_float2(0.f, 0.f);
+    const float2 plus = cadd(cscale(pyA, SN[0]), cscale(pyB, SN[2]));
+    const float2 minus = cadd(cscale(pyA, SN[1]), cscale(pyB, SN[3]));
+    const float2 inner = cadd(cmul(eM, plus), cmul(eP, minus));
+    s_nyq[slot][l] = cmul(cscale(p.psf_nyq[l], 0.5f * fs), inner);
+  }
+  __syncthreads();
+
+  float2 Z[M];
+  static_for<0, M>([&](auto mm) {
+    constexpr int m = decltype(mm)::value;
+    const float2 P = p.psf_main[m * W + l];
+    if constexpr (2 * m == W / 2) {
+      const float2 q0 = s_py[slot][W / 2 + h];
+      const float2 pyA = h ? q0 : cscale(q0, 0.5f);
+      const float2 pyB = h ? make_float2(0.f, 0.f) : cscale(s_py[slot][W], 0.5f);
+      Z[m] = cmul(cmul(P, pxF), cadd(cscale(pyA, S[m]), cscale(pyB, S[M])));
+    } else {
+      Z[m] = cscale(cmul(cmul(P, s_py[slot][2 * m + h]), pxF), S[m]);
+    }
+  });
+  if (c == 0) {
+    static_for<0, M>([&](auto mm) {
+      constexpr int m = decltype(mm)::value;
+      const float2 xn = s_nyq[slot][2 * m + h];
+      Z[m] = make_float2(Z[m].x - xn.y, Z[m].y + xn.x);
+    });
+  }
+  fft<M, +1>(Z);
+  static_for<0, M>([&](auto jj) {
+    constexpr int j = decltype(jj)::value;
+    s_t1[slot][j * T1S + l] = Z[j];
+  });
+  __syncthreads();
+
+  // ---------------------------------------------------------------- row phase
+  constexpr int NC = W / 2;
+  const int y = l;
+  const int jr = y & (M - 1);
+  const float2 tw = twiddle_rt<+1, W>(y);
+  float2 X[NC + 1];
+  static_for<0, NC>([&](auto cc) {
+    constexpr int cI = decltype(cc)::value;
+    const float2 e0 = s_t1[slot][jr * T1S + 2 * cI];
+    const float2 e1 = s_t1[slot][jr * T1S + 2 * cI + 1];
+    const float2 v = cadd(e0, cmul(tw, e1));
+    if constexpr (cI == 0) {
+      X[0] = make_float2(v.x, 0.f);
+      X[NC] = make_float2(v.y, 0.f);
+    } else {
+      X[cI] = v;
+    }
+  });
+  // complex-to-real: R[k] = (X[k] + conj X[W/2-k]) + i w^k (X[k] - conj X[W/2-k])
+  float2 R[NC];
+  static_for<0, NC>([&](auto kk) {
+    constexpr int k = decltype(kk)::value;
+    const float2 a = X[k], b = cconj(X[NC - k]);
+    R[k] = cadd(cadd(a, b), twiddle<+1, W, k + W / 4>(csub(a, b)));
+  });
+  fft<NC, +1>(R);
+  __syncthreads();  // every lane has read s_t1; reuse it as the W x (W+1) store tile
+  float* st = reinterpret_cast<float*>(&s_t1[slot][0]);
+  {
+    const int rowbase = ((y + G.ny) & (W - 1)) * (W + 1);
+    static_for<0, NC>([&](auto nn) {
+      constexpr int n = decltype(nn)::value;
+      st[rowbase + ((2 * n + G.nx) & (W - 1))] = R[n].x;
+      st[rowbase + ((2 * n + 1 + G.nx) & (W - 1))] = R[n].y;
+    });
+  }
+  __syncthreads();
+
+  // ---------------------------------------------------------------- real space + store
+  const float dx = (float)l - G.x0 - p.pg[0];
+  float* outp = p.out + (live ? stamp : 0) * (int64_t)(W * W);
+  const float qnan = __builtin_nanf("");
+  for (int r0 = 0; r0 < W; r0 += C::CH) {
+    float val[C::CH];
+    static_for<0, C::CH>([&](auto rr) {
+      constexpr int r = decltype(rr)::value;
+      val[r] = st[(r0 + r) * (W + 1) + l];
+    });
+    for (int k = 0; k < kloop; ++k) {
+      const float v = var[k];
+      const float A = (k < G.K) ? amp[k] : 0.f;
+      const float ra = (1.f - route_weight<W>(v * trB, p.flags)) * A;
+      if (ra == 0.f) continue;
+      const float sxx = fmaf(v, G.b11, p.pg[2]);
+      const float sxy = fmaf(v, G.b12, p.pg[3]);
+      const float syy = fmaf(v, G.b22, p.pg[4]);
+      const float det = fmaf(sxx, syy, -(sxy * sxy));
+      const float rdet = 1.f / det;
+      const float ampr = ra * G.flux * p.pg[5] * kInv2Pi / sqrtf(det);
+      const float a0 = kHalfLog2e * (syy * rdet) * dx * dx;
+      const float a1 = -2.f * kHalfLog2e * (sxy * rdet) * dx;
+      const float a2 = kHalfLog2e * (sxx * rdet);
+      const float dy0 = (float)r0 - G.y0 - p.pg[1];
+      static_for<0, C::CH>([&](auto rr) {
+        constexpr int r = decltype(rr)::value;
+        const float dy = dy0 + (float)r;
+        val[r] = fmaf(ampr, __builtin_amdgcn_exp2f(fmaf(dy, fmaf(a2, dy, a1), a0)), val[r]);
+      });
+    }
+    if (live) {
+      static_for<0, C::CH>([&](auto rr) {
+        constexpr int r = decltype(rr)::value;
+        outp[(r0 + r) * W + l] = G.ok ? val[r] : qnan;
+      });
+    }
+  }
+  if (live && !G.ok && l == 0) atomicAdd(p.invalid, 1ull);
+}
+
+template <int W>
+hipError_t launch_render_small(const RenderArgs& args, hipStream_t stream) {
+  using C = SmallCfg<W>;
+  constexpr int64_t kMaxBlocks = 1 << 30;
+  RenderArgs p = args;
+  int64_t done = 0;
+  while (done < args.n) {
+    const int64_t chunk = std::min<int64_t>(args.n - done, kMaxBlocks * C::SPB);
+    p.x = args.x + done;
+    p.y = args.y + done;
+    p.flux = args.flux + done;
+    p.r_e = args.r_e + done;
+    p.e1 = args.e1 + done;
+    p.e2 = args.e2 + done;
+    p.mix_id = args.mix_id ? args.mix_id + done : nullptr;
+    p.out = args.out + done * (int64_t)W * W;
+    p.n = chunk;
+    const unsigned blocks = (unsigned)((chunk + C::SPB - 1) / C::SPB);
+    hipLaunchKernelGGL(render_small_kernel<W>, dim3(blocks), dim3(C::BLOCK), 0, stream, p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    done += chunk;
+  }
+  return hipSuccess;
+}
+
+template hipError_t launch_render_small<16>(const RenderArgs&, hipStream_t);
+template hipError_t launch_render_small<32>(const RenderArgs&, hipStream_t);
+template hipError_t launch_render_small<64>(const RenderArgs&, hipStream_t);
+template hipError_t launch_render_small<128>(const RenderArgs&, hipStream_t);
+
+}  // namespace gfc

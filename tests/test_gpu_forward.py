@@ -1,0 +1,211 @@
+"""GPU parity of the forward render (through the C ABI) against the FP64
+oracle: per stamp, max |gpu - oracle| <= 1e-5 x max |oracle|."""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle as o
+import workloads as wl
+from gpu_helpers import TOL_PEAK, lib_objects, oracle_stamps, peak_errors, render_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2012_15797_amd as gfc
+    return gfc.Context.default(0)
+
+
+@pytest.mark.parametrize("W", [16, 32, 64, 128, 256])
+def test_psf_spectrum_cache(ctx, W):
+    """Steps 1-2 (PSF-FT cache): the device spectrum equals the oracle's naive
+    DFT of the folded PSF, to float32 rounding."""
+    import paper_2012_15797_amd as gfc
+
+    P = wl.psf_moffat_halo(64).astype(np.float32)
+    psf = gfc.Psf(ctx, P)
+    spec = psf.spectrum(W).cpu().numpy().astype(np.complex128)
+    ref = o.psf_spectrum(P.astype(np.float64), W)[:, : W // 2 + 1]
+    assert np.abs(spec - ref).max() <= 2e-7 * np.abs(ref).max()
+    np.testing.assert_allclose(psf.gauss, o.psf_gauss_moments(P.astype(np.float64)), rtol=1e-9, atol=1e-12)
+    psf.close()
+
+
+def test_tiny_case_sixteen_offsets(ctx):
+    """Tiny case: one EXP6 galaxy in a 64x64 stamp at 16 sub-pixel offsets,
+    every component in Fourier space."""
+    cfg = wl.config1()
+    psf, mix = lib_objects(ctx, cfg)
+    gal = cfg["gal"]
+    gpu = render_gpu(ctx, psf, mix, gal, 64, flags=cfg["flags"])
+    idx = list(range(len(gal)))
+    ref = oracle_stamps(cfg, gal, idx, flags=cfg["flags"])
+    errs = peak_errors(gpu, ref, idx)
+    assert errs.max() <= TOL_PEAK, errs
+    psf.close(); mix.close()
+
+
+@pytest.mark.parametrize("W", [16, 32, 64, 128])
+def test_hybrid_each_size(ctx, W):
+    """Every small stamp size with hybrid routing over a spread of radii, so
+    that all-Fourier, ramped and real-space components all occur; 70
+    stamps (several workgroups and a ragged tail)."""
+    rng = np.random.Generator(np.random.PCG64(100 + W))
+    cfg = wl.config2(10)
+    n = 70
+    gal = wl.draw_galaxies(rng, n, W, (np.arange(n) % 2).astype(np.int32),
+                           r_e_range=(0.3, W / 4.0))
+    psf, mix = lib_objects(ctx, cfg)
+    gpu = render_gpu(ctx, psf, mix, gal, W)
+    idx = list(range(n))
+    ref = oracle_stamps(cfg, gal, idx)
+    errs = peak_errors(gpu, ref, idx)
+    assert errs.max() <= TOL_PEAK, (errs.max(), int(errs.argmax()))
+    psf.close(); mix.close()
+
+
+@pytest.mark.parametrize("flags", [1, 2, 4])
+def test_routing_flags(ctx, flags):
+    cfg = wl.config_metric(40)
+    gal = cfg["gal"]
+    psf, mix = lib_objects(ctx, cfg)
+    gpu = render_gpu(ctx, psf, mix, gal, 64, flags=flags)
+    idx = list(range(len(gal)))
+    errs = peak_errors(gpu, oracle_stamps(cfg, gal, idx, flags=flags), idx)
+    assert errs.max() <= TOL_PEAK, errs.max()
+    psf.close(); mix.close()
+
+
+def test_metric_workload_sample(ctx):
+    """The throughput workload (DEV8, 64x64, Moffat PSF, hybrid routing):
+    500 consecutive stamps against the oracle."""
+    cfg = wl.config_metric(500)
+    gal = cfg["gal"]
+    psf, mix = lib_objects(ctx, cfg)
+    gpu = render_gpu(ctx, psf, mix, gal, 64)
+    idx = list(range(len(gal)))
+    errs = peak_errors(gpu, oracle_stamps(cfg, gal, idx), idx)
+    assert errs.max() <= TOL_PEAK, errs.max()
+    psf.close(); mix.close()
+
+
+def test_metric_workload_full_size_sampled(ctx):
+    """All 100,000 stamps of the throughput workload in one launch (the
+    benchmark's configuration); 300 sampled stamps against the oracle, and
+    properties of every stamp: finite, and the total equals flux x sum(A)
+    x sum(PSF) up to the light the real-space components put outside the
+    stamp."""
+    import torch
+    import paper_2012_15797_amd as gfc
+
+    cfg = wl.config_metric()
+    gal = cfg["gal"]
+    psf, mix = lib_objects(ctx, cfg)
+    out = gfc.gfc_render_stamps(ctx, psf, mix, gal.x, gal.y, gal.flux, gal.r_e, gal.e1, gal.e2, 64)
+    torch.cuda.synchronize()
+    assert torch.isfinite(out).all()
+    tot = out.double().sum(dim=(1, 2)).cpu().numpy()
+    amp, _ = cfg["mix"].as_f32().table(0)
+    expect = gal.flux.astype(np.float64) * amp.sum() * cfg["psf"].astype(np.float64).sum()
+    assert (tot <= expect * (1 + 1e-5)).all() and (tot >= 0.95 * expect).all()
+    idx = np.random.Generator(np.random.PCG64(9)).choice(len(gal), 300, replace=False)
+    sample = out[torch.as_tensor(idx, device=out.device)].cpu().numpy().astype(np.float64)
+    ref = oracle_stamps(cfg, gal, idx)
+    errs = np.array([np.abs(sample[j] - ref[j]).max() / np.abs(ref[j]).max() for j in range(len(idx))])
+    assert errs.max() <= TOL_PEAK, errs.max()
+    psf.close(); mix.close()
+
+
+def test_cd_matrix(ctx):
+    """Step 3 with a non-identity local WCS matrix: A = CD^{-1} E."""
+    cfg = wl.config_metric(30)
+    gal = cfg["gal"]
+    cd = np.array([1.1, 0.2, -0.15, 0.9])
+    psf, mix = lib_objects(ctx, cfg)
+    gpu = render_gpu(ctx, psf, mix, gal, 64, cd=cd.astype(np.float32))
+    idx = list(range(len(gal)))
+    ref = oracle_stamps(cfg, gal, idx, cd=cd.astype(np.float32).astype(np.float64))
+    errs = peak_errors(gpu, ref, idx)
+    assert errs.max() <= TOL_PEAK, errs.max()
+    psf.close(); mix.close()
+
+
+def test_explicit_psf_gaussian_and_large_galaxies(ctx):
+    """Large-galaxy case at W = 128 (1-4 components in real space) with an
+    explicitly fitted single-Gaussian PSF."""
+    cfg = wl.config3(200)
+    gal = cfg["gal"].subset(np.nonzero(cfg["gal"].W == 128)[0][:40])
+    psf, mix = lib_objects(ctx, cfg)
+    gpu = render_gpu(ctx, psf, mix, gal, 128)
+    idx = list(range(len(gal)))
+    errs = peak_errors(gpu, oracle_stamps(cfg, gal, idx), idx)
+    assert errs.max() <= TOL_PEAK, errs.max()
+    psf.close(); mix.close()
+
+
+def test_edge_positions_and_integer_shift(ctx):
+    """Centres near and across the stamp edge, negative and large
+    coordinates (the integer part becomes a cyclic roll of the Fourier
+    image); every component forced to Fourier space so the roll is exact."""
+    cfg = wl.config_metric(8)
+    base = cfg["gal"]
+    xs = np.array([0.0, 0.4, 63.9, -3.25, 100.6, 31.0, 32.5, -64.2], np.float32)
+    ys = np.array([63.7, 0.0, 17.2, 5.5, -40.1, 31.0, 96.0, 2.0], np.float32)
+    gal = wl.Galaxies(xs, ys, base.flux, base.r_e, base.e1, base.e2, base.mix_id, base.W)
+    psf, mix = lib_objects(ctx, cfg)
+    for flags in (o.FORCE_FOURIER, 0):
+        gpu = render_gpu(ctx, psf, mix, gal, 64, flags=flags)
+        idx = list(range(len(gal)))
+        errs = peak_errors(gpu, oracle_stamps(cfg, gal, idx, flags=flags), idx)
+        assert errs.max() <= TOL_PEAK, (flags, errs)
+    psf.close(); mix.close()
+
+
+def test_invalid_galaxies_give_nan_and_count(ctx):
+    import paper_2012_15797_amd as gfc
+
+    local = gfc.Context(0)
+    cfg = wl.config_metric(6)
+    g = cfg["gal"]
+    e1 = g.e1.copy(); r_e = g.r_e.copy(); x = g.x.copy()
+    e1[1] = 0.99; g.e2[1] = 0.5     # |e| >= 1
+    r_e[2] = -1.0
+    x[3] = np.nan
+    mid = np.zeros(6, np.int32); mid[4] = 7   # no such table
+    gal = wl.Galaxies(x, g.y, g.flux, r_e, e1, g.e2, mid, g.W)
+    psf, mix = lib_objects(local, cfg)
+    gpu = render_gpu(local, psf, mix, gal, 64)
+    bad = [1, 2, 3, 4]
+    assert np.isnan(gpu[bad]).all()
+    assert np.isfinite(gpu[[0, 5]]).all()
+    assert local.invalid_count() == 4
+    psf.close(); mix.close()
+
+
+def test_deterministic(ctx):
+    cfg = wl.config_metric(300)
+    gal = cfg["gal"]
+    psf, mix = lib_objects(ctx, cfg)
+    a = render_gpu(ctx, psf, mix, gal, 64)
+    b = render_gpu(ctx, psf, mix, gal, 64)
+    assert np.array_equal(a, b)
+    psf.close(); mix.close()
+
+
+def test_empty_batch_and_errors(ctx):
+    import paper_2012_15797_amd as gfc
+
+    cfg = wl.config_metric(0)
+    psf, mix = lib_objects(ctx, cfg)
+    e = np.zeros(0, np.float32)
+    out = gfc.gfc_render_stamps(ctx, psf, mix, e, e, e, e, e, e, 64)
+    assert out.shape == (0, 64, 64)
+    one = np.ones(1, np.float32)
+    with pytest.raises(gfc.GfcError):
+        gfc.gfc_render_stamps(ctx, psf, mix, one, one, one, one, one, one, 48)
+    with pytest.raises(gfc.GfcError):
+        gfc.gfc_render_stamps(ctx, psf, mix, one, one, one, one, one, one, 64, flags=3)
+    psf.close(); mix.close()
