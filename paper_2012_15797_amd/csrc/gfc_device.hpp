@@ -72,6 +72,9 @@ __device__ __forceinline__ Galaxy load_galaxy(const RenderArgs& p, int64_t g) {
          fabsf(G.y0) <= 8388608.f && G.table >= 0 && G.table < p.n_tables;
   if (!G.ok) G.table = 0;
   G.K = p.K[G.table];
+  // An invalid galaxy renders as NaN everywhere: a NaN flux propagates
+  // through every product of the Fourier and real-space paths.
+  if (!G.ok) G.flux = __builtin_nanf("");
   const float fxf = floorf(G.x0), fyf = floorf(G.y0);
   G.fx = G.ok ? G.x0 - fxf : 0.f;
   G.fy = G.ok ? G.y0 - fyf : 0.f;
@@ -97,7 +100,7 @@ template <int W>
 __device__ __forceinline__ float route_weight(float tr, unsigned flags) {
   if (flags & kForceFourier) return 1.f;
   if (flags & kForceReal) return 0.f;
-  const float n = (0.5f * (float)W) / sqrtf(tr);
+  const float n = (0.5f * (float)W) * __builtin_amdgcn_rsqf(tr);
   const float t = fminf(fmaxf(n - 3.f, 0.f), 1.f);
   if (flags & kRampLinear) return t;
   return t * t * (3.f - 2.f * t);

@@ -14,6 +14,9 @@ namespace gfc {
 template <int W>
 hipError_t launch_render_small(const RenderArgs& args, hipStream_t stream);
 
+// Forward render, W = 256 (device scratch allocated stream-ordered per call).
+hipError_t launch_render_w256(const RenderArgs& args, hipStream_t stream);
+
 // PSF spectrum (Section 2, steps 1-2): separable float64 DFT of the S_y x S_x
 // PSF with its centre pixel at frequency-grid index 0.  Writes the
 // lane-permuted main columns, the Nyquist column and optionally the natural

@@ -53,8 +53,11 @@ __global__ void psf_col_dft(const double2* __restrict__ tmp, int Sy, int W,
   }
   const float2 v = make_float2((float)re, (float)im);
   if (kx < W / 2) {
-    // lane-permuted: lane (c = kx, h = ky & 1) reads element (ky >> 1) * W + 2 kx + h
-    main_cols[(ky >> 1) * W + 2 * kx + (ky & 1)] = v;
+    // Lane-permuted for the render kernels: lane (c = kx, h = ky mod D) of a
+    // stamp reads element (ky / D) * (D W / 2) + D kx + h, where D is the
+    // decimation of the column transform (4 for W = 256, 2 otherwise).
+    const int D = (W == 256) ? 4 : 2;
+    main_cols[(ky / D) * (D * (W / 2)) + D * kx + (ky % D)] = v;
   } else {
     nyq_col[ky] = v;
   }

@@ -11,7 +11,7 @@ gfc_status render_launch(const RenderArgs& a, int W, hipStream_t stream) {
     case 32: e = launch_render_small<32>(a, stream); break;
     case 64: e = launch_render_small<64>(a, stream); break;
     case 128: e = launch_render_small<128>(a, stream); break;
-    case 256: return fail(GFC_EUNSUPPORTED, "W = 256 not built yet");
+    case 256: e = launch_render_w256(a, stream); break;
     default: return fail(GFC_EINVAL, "unsupported stamp size");
   }
   if (e != hipSuccess) return hip_fail(e, "render launch");

@@ -31,7 +31,7 @@ struct SmallCfg {
   static constexpr int SPB = BLOCK / W;          // stamps per workgroup
   static constexpr int T1S = W + 1;              // float2 per LDS row (padding kills bank conflicts)
   static constexpr int T1N = M * T1S;            // float2 per stamp; also W x (W+1) floats
-  static constexpr int CH = W < 32 ? W : 32;     // output rows per chunk
+  static constexpr int CH = W <= 64 ? W : 32;    // output rows per chunk
 };
 
 template <int W>
@@ -48,7 +48,11 @@ render_small_kernel(RenderArgs p) {
   const int slot = threadIdx.x / W;
   const int64_t stamp = (int64_t)blockIdx.x * C::SPB + slot;
   const bool live = stamp < p.n;
-  const Galaxy G = load_galaxy<W>(p, live ? stamp : p.n - 1);
+  Galaxy G = load_galaxy<W>(p, live ? stamp : p.n - 1);
+  if constexpr (C::SPB == 1) {  // one stamp per wavefront: keep its integer shift in SGPRs
+    G.nx = __builtin_amdgcn_readfirstlane(G.nx);
+    G.ny = __builtin_amdgcn_readfirstlane(G.ny);
+  }
   const float* amp = p.amp + G.table * kKmax;
   const float* var = p.var + G.table * kKmax;
   const int kloop = (C::SPB == 1) ? G.K : p.kmax;
@@ -86,10 +90,13 @@ render_small_kernel(RenderArgs p) {
   float S[M + 1];
   float SN[4] = {0.f, 0.f, 0.f, 0.f};
   static_for<0, M + 1>([&](auto mm) { S[decltype(mm)::value] = 0.f; });
+  unsigned rmask = 0;  // components with a real-space share
   for (int k = 0; k < kloop; ++k) {
     const float v = var[k];
     const float A = (k < G.K) ? amp[k] : 0.f;
-    const float wa = route_weight<W>(v * trB, p.flags) * A;
+    const float w = route_weight<W>(v * trB, p.flags);
+    if (w < 1.f && A != 0.f) rmask |= 1u << k;
+    const float wa = w * A;
     if (wa == 0.f) continue;
     static_for<0, M + 1>([&](auto mm) {
       constexpr int m = decltype(mm)::value;
@@ -171,47 +178,50 @@ render_small_kernel(RenderArgs p) {
       X[cI] = v;
     }
   });
-  // complex-to-real: R[k] = (X[k] + conj X[W/2-k]) + i w^k (X[k] - conj X[W/2-k])
+  // complex-to-real: R[k] = (X[k] + conj X[W/2-k]) + i w^k (X[k] - conj X[W/2-k]),
+  // w = exp(2 pi i / W).  Bins k and W/2-k share s = X[k] + conj X[W/2-k] and
+  // t = w^k (X[k] - conj X[W/2-k]):  R[k] = s + i t,  R[W/2-k] = conj(s) + i conj(t).
   float2 R[NC];
-  static_for<0, NC>([&](auto kk) {
+  static_for<0, NC / 2 + 1>([&](auto kk) {
     constexpr int k = decltype(kk)::value;
     const float2 a = X[k], b = cconj(X[NC - k]);
-    R[k] = cadd(cadd(a, b), twiddle<+1, W, k + W / 4>(csub(a, b)));
+    const float2 sum = cadd(a, b);
+    const float2 t = twiddle<+1, W, k>(csub(a, b));
+    R[k] = make_float2(sum.x - t.y, sum.y + t.x);
+    if constexpr (k != 0 && 2 * k != NC) R[NC - k] = make_float2(sum.x + t.y, t.x - sum.y);
   });
   fft<NC, +1>(R);
   __syncthreads();  // every lane has read s_t1; reuse it as the W x (W+1) store tile
   float* st = reinterpret_cast<float*>(&s_t1[slot][0]);
-  {
-    const int rowbase = ((y + G.ny) & (W - 1)) * (W + 1);
-    static_for<0, NC>([&](auto nn) {
-      constexpr int n = decltype(nn)::value;
-      st[rowbase + ((2 * n + G.nx) & (W - 1))] = R[n].x;
-      st[rowbase + ((2 * n + 1 + G.nx) & (W - 1))] = R[n].y;
-    });
-  }
+  static_for<0, NC>([&](auto nn) {
+    constexpr int n = decltype(nn)::value;
+    st[y * (W + 1) + 2 * n] = R[n].x;
+    st[y * (W + 1) + 2 * n + 1] = R[n].y;
+  });
   __syncthreads();
 
   // ---------------------------------------------------------------- real space + store
   const float dx = (float)l - G.x0 - p.pg[0];
   float* outp = p.out + (live ? stamp : 0) * (int64_t)(W * W);
-  const float qnan = __builtin_nanf("");
+  // Output pixel (Y, X = l) is pixel ((Y - ny) mod W, (X - nx) mod W) of the
+  // fractional-offset Fourier image: the integer shift is a cyclic roll.
+  const int colsrc = (l - G.nx) & (W - 1);
   for (int r0 = 0; r0 < W; r0 += C::CH) {
     float val[C::CH];
     static_for<0, C::CH>([&](auto rr) {
       constexpr int r = decltype(rr)::value;
-      val[r] = st[(r0 + r) * (W + 1) + l];
+      val[r] = st[((r0 + r - G.ny) & (W - 1)) * (W + 1) + colsrc];
     });
-    for (int k = 0; k < kloop; ++k) {
+    for (unsigned mk = rmask; mk != 0; mk &= mk - 1) {
+      const int k = __builtin_ctz(mk);
       const float v = var[k];
-      const float A = (k < G.K) ? amp[k] : 0.f;
-      const float ra = (1.f - route_weight<W>(v * trB, p.flags)) * A;
-      if (ra == 0.f) continue;
+      const float ra = (1.f - route_weight<W>(v * trB, p.flags)) * amp[k];
       const float sxx = fmaf(v, G.b11, p.pg[2]);
       const float sxy = fmaf(v, G.b12, p.pg[3]);
       const float syy = fmaf(v, G.b22, p.pg[4]);
       const float det = fmaf(sxx, syy, -(sxy * sxy));
-      const float rdet = 1.f / det;
-      const float ampr = ra * G.flux * p.pg[5] * kInv2Pi / sqrtf(det);
+      const float rdet = __builtin_amdgcn_rcpf(det);
+      const float ampr = ra * G.flux * p.pg[5] * kInv2Pi * __builtin_amdgcn_rsqf(det);
       const float a0 = kHalfLog2e * (syy * rdet) * dx * dx;
       const float a1 = -2.f * kHalfLog2e * (sxy * rdet) * dx;
       const float a2 = kHalfLog2e * (sxx * rdet);
@@ -225,7 +235,7 @@ render_small_kernel(RenderArgs p) {
     if (live) {
       static_for<0, C::CH>([&](auto rr) {
         constexpr int r = decltype(rr)::value;
-        outp[(r0 + r) * W + l] = G.ok ? val[r] : qnan;
+        outp[(r0 + r) * W + l] = val[r];
       });
     }
   }

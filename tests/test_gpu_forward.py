@@ -48,14 +48,14 @@ def test_tiny_case_sixteen_offsets(ctx):
     psf.close(); mix.close()
 
 
-@pytest.mark.parametrize("W", [16, 32, 64, 128])
+@pytest.mark.parametrize("W", [16, 32, 64, 128, 256])
 def test_hybrid_each_size(ctx, W):
-    """Every small stamp size with hybrid routing over a spread of radii, so
-    that all-Fourier, ramped and real-space components all occur; 70
-    stamps (several workgroups and a ragged tail)."""
+    """Every stamp size with hybrid routing over a spread of radii, so that
+    all-Fourier, ramped and real-space components all occur; 70 stamps
+    (several workgroups and a ragged tail), 16 at W = 256."""
     rng = np.random.Generator(np.random.PCG64(100 + W))
     cfg = wl.config2(10)
-    n = 70
+    n = 70 if W < 256 else 16
     gal = wl.draw_galaxies(rng, n, W, (np.arange(n) % 2).astype(np.int32),
                            r_e_range=(0.3, W / 4.0))
     psf, mix = lib_objects(ctx, cfg)
@@ -133,31 +133,36 @@ def test_cd_matrix(ctx):
     psf.close(); mix.close()
 
 
-def test_explicit_psf_gaussian_and_large_galaxies(ctx):
-    """Large-galaxy case at W = 128 (1-4 components in real space) with an
-    explicitly fitted single-Gaussian PSF."""
-    cfg = wl.config3(200)
-    gal = cfg["gal"].subset(np.nonzero(cfg["gal"].W == 128)[0][:40])
+@pytest.mark.parametrize("W", [128, 256])
+def test_large_galaxy_workload(ctx, W):
+    """Large-galaxy case (r_e 10..60 px, DEV8, 1-4 components in real space)
+    at 128 and 256 with the fitted single-Gaussian PSF, 20 stamps each."""
+    cfg = wl.config3(400)
+    sel = np.nonzero(cfg["gal"].W == W)[0][:20]
+    gal = cfg["gal"].subset(sel)
     psf, mix = lib_objects(ctx, cfg)
-    gpu = render_gpu(ctx, psf, mix, gal, 128)
+    gpu = render_gpu(ctx, psf, mix, gal, W)
     idx = list(range(len(gal)))
     errs = peak_errors(gpu, oracle_stamps(cfg, gal, idx), idx)
     assert errs.max() <= TOL_PEAK, errs.max()
     psf.close(); mix.close()
 
 
-def test_edge_positions_and_integer_shift(ctx):
+@pytest.mark.parametrize("W", [64, 256])
+def test_edge_positions_and_integer_shift(ctx, W):
     """Centres near and across the stamp edge, negative and large
     coordinates (the integer part becomes a cyclic roll of the Fourier
     image); every component forced to Fourier space so the roll is exact."""
     cfg = wl.config_metric(8)
     base = cfg["gal"]
-    xs = np.array([0.0, 0.4, 63.9, -3.25, 100.6, 31.0, 32.5, -64.2], np.float32)
-    ys = np.array([63.7, 0.0, 17.2, 5.5, -40.1, 31.0, 96.0, 2.0], np.float32)
-    gal = wl.Galaxies(xs, ys, base.flux, base.r_e, base.e1, base.e2, base.mix_id, base.W)
+    s = W / 64.0
+    xs = (np.array([0.0, 0.4, 63.9, -3.25, 100.6, 31.0, 32.5, -64.2]) * s).astype(np.float32)
+    ys = (np.array([63.7, 0.0, 17.2, 5.5, -40.1, 31.0, 96.0, 2.0]) * s).astype(np.float32)
+    gal = wl.Galaxies(xs, ys, base.flux, base.r_e, base.e1, base.e2, base.mix_id,
+                      np.full(8, W, np.int32))
     psf, mix = lib_objects(ctx, cfg)
     for flags in (o.FORCE_FOURIER, 0):
-        gpu = render_gpu(ctx, psf, mix, gal, 64, flags=flags)
+        gpu = render_gpu(ctx, psf, mix, gal, W, flags=flags)
         idx = list(range(len(gal)))
         errs = peak_errors(gpu, oracle_stamps(cfg, gal, idx, flags=flags), idx)
         assert errs.max() <= TOL_PEAK, (flags, errs)
