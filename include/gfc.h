@@ -124,6 +124,12 @@ gfc_status gfc_mix_create(gfc_ctx* ctx, int n_tables, const int* K, const float*
 /* Device pointers to the table arrays (amp, var: [n_tables][GFC_KMAX]);
  * writes through amp_dev change the amplitudes used by later calls. */
 gfc_status gfc_mix_device_tables(gfc_mix* mix, float** amp_dev, float** var_dev);
+/* Replaces the amplitudes with amp_dev (device, [n_tables][GFC_KMAX]
+ * float32; entries past K[t] ignored), asynchronously on hip_stream: later
+ * calls on that stream see the new values.  This is how a fit updates the
+ * amplitudes it differentiates (Section 3: the mixture amplitudes vary with
+ * the profile). */
+gfc_status gfc_mix_set_amp(gfc_mix* mix, const float* amp_dev, void* hip_stream);
 gfc_status gfc_mix_destroy(gfc_mix* mix);
 
 /* --------------------------------------------------------------- render */

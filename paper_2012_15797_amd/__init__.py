@@ -24,3 +24,4 @@ from .api import (  # noqa: F401
     gfc_render_stamps,
     gfc_render_stamps_backward,
 )
+from .autograd import RenderStamps, render  # noqa: F401,E402

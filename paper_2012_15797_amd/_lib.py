@@ -72,6 +72,7 @@ PROTOTYPES = {
     "gfc_mix_create": (I32, [P, I32, ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_float),
                              ctypes.POINTER(ctypes.c_float), PP]),
     "gfc_mix_device_tables": (I32, [P, PP, PP]),
+    "gfc_mix_set_amp": (I32, [P, P, P]),
     "gfc_mix_destroy": (I32, [P]),
     "gfc_render_stamps": (I32, [P, P, P, ctypes.POINTER(gfc_galaxies), I64, I32, U32, P, P]),
     "gfc_backward_workspace_bytes": (ctypes.c_size_t, [I64]),

@@ -383,6 +383,15 @@ gfc_status gfc_mix_device_tables(gfc_mix* mix, float** amp_dev, float** var_dev)
   return GFC_OK;
 }
 
+gfc_status gfc_mix_set_amp(gfc_mix* mix, const float* amp_dev, void* hip_stream) {
+  if (!mix || !amp_dev) return fail(GFC_EINVAL, "null argument");
+  DeviceGuard guard(mix->ctx->device);
+  hipError_t e = hipMemcpyAsync(mix->d_amp, amp_dev, (size_t)mix->n_tables * GFC_KMAX * sizeof(float),
+                                hipMemcpyDeviceToDevice, (hipStream_t)hip_stream);
+  if (e != hipSuccess) return hip_fail(e, "amplitude copy");
+  return GFC_OK;
+}
+
 gfc_status gfc_mix_destroy(gfc_mix* mix) {
   if (!mix) return fail(GFC_EINVAL, "null mixture");
   DeviceGuard guard(mix->ctx->device);

@@ -1,10 +1,546 @@
-// Adjoint of the forward render (placeholder until the adjoint kernels land).
+// Adjoint of the forward render for W = 16, 32, 64, 128 (Lang 2020, Section
+// 2, steps 3-8, differentiated).
+//
+// For a loss L with upstream gradient g = dL/dI, the Fourier-path part is
+// evaluated in the frequency domain:
+//   <g, I_F> = W^-2 sum_k X[k] conj(G[k]),   G = DFT(g),
+// so with Gamma0[k] = h(k_x) W^-2 P_hat[k] conj(G[k]) (h = 1 on the columns
+// k_x = 0, W/2 and 2 elsewhere, summing over the half spectrum) and U0 =
+// Gamma0 * (fractional-shift phase), each parameter's derivative is a sum over
+// bins of Re(U0 * dS/dtheta), where S = sum_i w_i A_i exp(-2 pi^2 v_i q_B) is
+// the real mixture sum.  Every component shares the shape matrix B (C_i =
+// v_i B), so the shape derivatives need only S and S1 = sum_i w_i A_i v_i E_i
+// per bin.  The integer part of the centre is removed by un-rolling g.  The
+// real-space part is accumulated pixel by pixel.  Per-component sums feed the
+// amplitude gradients and the routing-weight terms of the smooth ramp.
+//
+// Each stamp is handled by W lanes, as in the forward kernel:
+//  load        lane = output column: real-space sums, g un-rolled into LDS
+//  row R2C     lane = row: real-to-complex forward transform (W/2-point FFT)
+//  column DFT  lane (c, h): decimation in frequency, rows k_y = 2m + h
+//  bins        exponentials per component, accumulations, lane reductions
+//  chain rule  B -> (log r_e, e1, e2) and the routing weights, one lane.
+#include "gfc_device.hpp"
 #include "gfc_internal.hpp"
+#include "gfc_launch.hpp"
+
+namespace gfc {
+
+template <int W>
+struct BwdCfg {
+  static constexpr int M = W / 2;
+  static constexpr int BLOCK = W < 64 ? 64 : W;
+  static constexpr int SPB = BLOCK / W;
+  static constexpr int TS = W + 2;            // floats per row of the g tile / float2 per row of Gr is W/2+1
+  static constexpr int TN = W * (W + 2);      // floats per stamp
+  static constexpr int CH = W <= 64 ? W : 32; // rows per load chunk
+  static constexpr int NP = M + 5;            // evaluation points per lane
+  static constexpr int PB = M <= 16 ? NP : 16;  // points per block of the component loop
+  static constexpr int WPE = W <= 32 ? 4 : (W == 64 ? 3 : 1);  // occupancy target (waves per SIMD)
+};
+
+// Sum over the W lanes of one stamp; every lane of the stamp receives the total.
+// Fixed butterfly order (deterministic).  For W = 128 the two wavefronts meet
+// in LDS.
+template <int W>
+__device__ __forceinline__ float seg_sum(float v, float* s_x2) {
+  constexpr int LIM = W < 64 ? W : 64;
+#pragma unroll
+  for (int o = 1; o < LIM; o <<= 1) v += __shfl_xor(v, o);
+  if constexpr (W == 128) {
+    const int wv = (threadIdx.x >> 6) & 1;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) s_x2[wv] = v;
+    __syncthreads();
+    v = s_x2[0] + s_x2[1];
+  }
+  return v;
+}
+
+template <int W>
+__global__ void __launch_bounds__(BwdCfg<W>::BLOCK) __attribute__((amdgpu_waves_per_eu(BwdCfg<W>::WPE)))
+render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __restrict__ grad_params,
+                        float* __restrict__ amp_part) {
+  using C = BwdCfg<W>;
+  constexpr int M = C::M;
+  constexpr int NP = C::NP;
+  constexpr int TS = C::TS;
+  __shared__ float s_tile[C::SPB][C::TN];
+  __shared__ float2 s_py[C::SPB][W + 2];
+  __shared__ float2 s_nyq[C::SPB][W];
+  __shared__ float s_pk[C::SPB][kKmax][W];
+  __shared__ float s_racc[C::SPB][kKmax][6];
+  __shared__ float s_x2[2];
+
+  const int l = threadIdx.x % W;
+  const int slot = threadIdx.x / W;
+  const int64_t stamp = (int64_t)blockIdx.x * C::SPB + slot;
+  const bool live = stamp < p.n;
+  const int64_t gidx = live ? stamp : p.n - 1;
+  Galaxy G = load_galaxy<W>(p, gidx);
+  if constexpr (C::SPB == 1) {
+    G.nx = __builtin_amdgcn_readfirstlane(G.nx);
+    G.ny = __builtin_amdgcn_readfirstlane(G.ny);
+  }
+  const float* amp = p.amp + G.table * kKmax;
+  const float* var = p.var + G.table * kKmax;
+  const float trB = G.b11 + G.b22;
+  const int kloop = (C::SPB == 1) ? G.K : p.kmax;
+
+  // routing: components with a real-space share
+  unsigned rmask = 0;
+  for (int k = 0; k < kloop; ++k) {
+    const float A = (k < G.K) ? amp[k] : 0.f;
+    if (A != 0.f && route_weight<W>(var[k] * trB, p.flags) < 1.f) rmask |= 1u << k;
+  }
+
+  // ------------------------------------------------------------ load + real space
+  const float* gp = gout + gidx * (int64_t)(W * W);
+  float* tile = s_tile[slot];
+  {
+    const float dx = (float)l - G.x0 - p.pg[0];
+    const int coldst = (l - G.nx) & (W - 1);
+    for (int k = 0; k < kKmax; ++k) {
+      if (l < 6) s_racc[slot][k][l] = 0.f;
+    }
+    for (int r0 = 0; r0 < W; r0 += C::CH) {
+      float gv[C::CH];
+      static_for<0, C::CH>([&](auto rr) {
+        constexpr int r = decltype(rr)::value;
+        gv[r] = gp[(r0 + r) * W + l];
+        tile[((r0 + r - G.ny) & (W - 1)) * TS + coldst] = gv[r];
+      });
+      for (unsigned mk = rmask; mk != 0; mk &= mk - 1) {
+        const int k = __builtin_ctz(mk);
+        const float v = var[k];
+        const float sxx = fmaf(v, G.b11, p.pg[2]);
+        const float sxy = fmaf(v, G.b12, p.pg[3]);
+        const float syy = fmaf(v, G.b22, p.pg[4]);
+        const float det = fmaf(sxx, syy, -(sxy * sxy));
+        const float rdet = __builtin_amdgcn_rcpf(det);
+        const float ixx = syy * rdet, ixy = -sxy * rdet, iyy = sxx * rdet;
+        const float nrm = kInv2Pi * __builtin_amdgcn_rsqf(det);
+        float a0 = 0.f, ax = 0.f, ay = 0.f, axx = 0.f, axy = 0.f, ayy = 0.f;
+        const float dy0 = (float)r0 - G.y0 - p.pg[1];
+        static_for<0, C::CH>([&](auto rr) {
+          constexpr int r = decltype(rr)::value;
+          const float dy = dy0 + (float)r;
+          const float zx = fmaf(ixx, dx, ixy * dy);
+          const float zy = fmaf(ixy, dx, iyy * dy);
+          const float qf = fmaf(dx, zx, dy * zy);
+          const float gn = gv[r] * nrm * __builtin_amdgcn_exp2f(kHalfLog2e * qf);
+          const float gx = gn * zx, gy = gn * zy;
+          a0 += gn;
+          ax += gx;
+          ay += gy;
+          axx = fmaf(gx, zx, axx);
+          axy = fmaf(gx, zy, axy);
+          ayy = fmaf(gy, zy, ayy);
+        });
+        a0 = seg_sum<W>(a0, s_x2);
+        ax = seg_sum<W>(ax, s_x2);
+        ay = seg_sum<W>(ay, s_x2);
+        axx = seg_sum<W>(axx, s_x2);
+        axy = seg_sum<W>(axy, s_x2);
+        ayy = seg_sum<W>(ayy, s_x2);
+        if (l == 0) {
+          s_racc[slot][k][0] += a0;
+          s_racc[slot][k][1] += ax;
+          s_racc[slot][k][2] += ay;
+          s_racc[slot][k][3] += axx;
+          s_racc[slot][k][4] += axy;
+          s_racc[slot][k][5] += ayy;
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ------------------------------------------------------------ row R2C (lane = row y)
+  // Gr2[k] = 2 sum_x g[y][x] exp(-2 pi i k x / W), k = 0..W/2.
+  {
+    const int y = l;
+    float2 Zr[M];
+    static_for<0, M>([&](auto nn) {
+      constexpr int n = decltype(nn)::value;
+      Zr[n] = make_float2(tile[y * TS + 2 * n], tile[y * TS + 2 * n + 1]);
+    });
+    fft<M, -1>(Zr);
+    __syncthreads();  // the tile is rewritten as Gr2 rows below
+    float2* gr = reinterpret_cast<float2*>(tile);  // [W][W/2 + 1]
+    static_for<0, M / 2 + 1>([&](auto kk) {
+      constexpr int k = decltype(kk)::value;
+      constexpr int kc = (M - k) % M;  // Zr[W/2] is Zr[0]
+      const float2 a = Zr[k], b = cconj(Zr[kc]);
+      const float2 e2 = cadd(a, b);
+      const float2 o2 = rot90<-1>(csub(a, b));      // -i (a - b)
+      const float2 t2 = twiddle<-1, W, k>(o2);
+      gr[y * (M + 1) + k] = cadd(e2, t2);
+      if constexpr (2 * k != M) gr[y * (M + 1) + (M - k)] = cconj(csub(e2, t2));
+    });
+  }
+  __syncthreads();
+
+  // ------------------------------------------------------------ column DFT (lane (c, h))
+  const int c = l >> 1, h = l & 1;
+  const float2* gr = reinterpret_cast<const float2*>(tile);
+  float2 Gk[M];  // 2 G[k_y = 2m + h][c]   (c = 0: packed with column W/2)
+  {
+    const float sg = h ? -1.f : 1.f;
+    static_for<0, M>([&](auto yy) {
+      constexpr int yq = decltype(yy)::value;
+      float2 a, b;
+      if (c == 0) {
+        a = make_float2(gr[yq * (M + 1)].x, gr[yq * (M + 1) + M].x);
+        b = make_float2(gr[(yq + M) * (M + 1)].x, gr[(yq + M) * (M + 1) + M].x);
+      } else {
+        a = gr[yq * (M + 1) + c];
+        b = gr[(yq + M) * (M + 1) + c];
+      }
+      const float2 v = make_float2(fmaf(sg, b.x, a.x), fmaf(sg, b.y, a.y));
+      const float2 tw = twiddle<-1, W, yq>(v);  // exp(-2 pi i yq / W) v
+      Gk[yq] = h ? tw : v;
+    });
+    fft<M, -1>(Gk);
+  }
+  // Unpack the packed column: Z = G0 + i GN, with G0 and GN Hermitian in k_y.
+  if (c == 0) {
+    static_for<0, M>([&](auto mm) {
+      constexpr int m = decltype(mm)::value;
+      s_nyq[slot][2 * m + h] = Gk[m];
+    });
+  }
+  __syncthreads();
+  float2 GN;  // 2 G[k_y = l][W/2]
+  {
+    const float2 za = s_nyq[slot][l], zb = cconj(s_nyq[slot][(W - l) & (W - 1)]);
+    const float2 d = csub(za, zb);
+    GN = make_float2(0.5f * d.y, -0.5f * d.x);  // (za - conj zb) / (2 i)
+  }
+  if (c == 0) {
+    static_for<0, M>([&](auto mm) {
+      constexpr int m = decltype(mm)::value;
+      const float2 zb = cconj(s_nyq[slot][(W - 2 * m - h) & (W - 1)]);
+      Gk[m] = cscale(cadd(Gk[m], zb), 0.5f);
+    });
+  }
+
+  // ------------------------------------------------------------ phases and U0 per point
+  const float nu = (float)c * (1.f / W);
+  const float hW = (float)h * (1.f / W);
+  float sx, cx;
+  sincospif(-2.f * G.fx * nu, &sx, &cx);
+  const float omN = (l < W / 2) ? (float)l * (1.f / W) : (l == W / 2 ? 0.5f : (float)(l - W) * (1.f / W));
+  float sy, cy, sym, cym, sxh, cxh;
+  sincospif(-2.f * G.fy * omN, &sy, &cy);
+  sincospif(G.fy, &sym, &cym);
+  sincospif(-G.fx, &sxh, &cxh);
+  s_py[slot][l] = make_float2(cy, sy);
+  if (l == 0) s_py[slot][W] = make_float2(cym, sym);
+  __syncthreads();
+
+  // Points: m = 0..M-1 (column c, row 2m+h), M (omega = -1/2 twin of the
+  // Nyquist row), M+1..M+4 (Nyquist column row l: nu = +-1/2, and the
+  // omega = -1/2 twins of the corner).  U0 already carries the Nyquist means.
+  float ure[NP], uim[NP];
+  // (nu, omega) of point j
+  auto point = [&](auto jj, float& n_, float& o_) {
+    constexpr int j = decltype(jj)::value;
+    if constexpr (j < M) {
+      n_ = nu;
+      if constexpr (2 * j < W / 2) o_ = (float)(2 * j) * (1.f / W) + hW;
+      else if constexpr (2 * j == W / 2) o_ = h ? (float)(W / 2 + 1 - W) * (1.f / W) : 0.5f;
+      else o_ = (float)(2 * j - W) * (1.f / W) + hW;
+    } else if constexpr (j == M) {
+      n_ = nu;
+      o_ = -0.5f;
+    } else {
+      n_ = (j - M) & 1 ? 0.5f : -0.5f;
+      o_ = j <= M + 2 ? omN : -0.5f;
+    }
+  };
+  {
+    // h(k_x) / W^2 with h = 1 on column 0 and 2 elsewhere, halved for the factor 2 in Gk
+    const float colw = (c == 0 ? 0.5f : 1.f) / ((float)W * (float)W);
+    const float2 px = make_float2(cx, sx);
+    static_for<0, M>([&](auto mm) {
+      constexpr int m = decltype(mm)::value;
+      const float2 P = p.psf_main[m * W + l];
+      const float2 gam = cscale(cmulc(P, Gk[m]), colw);   // P conj(G)
+      const float2 gp2 = cmul(gam, px);
+      float2 u;
+      if constexpr (2 * m == W / 2) {
+        const float2 q0 = s_py[slot][W / 2 + h];
+        const float2 pyA = h ? q0 : cscale(q0, 0.5f);
+        u = cmul(gp2, pyA);
+        const float2 pyB = h ? make_float2(0.f, 0.f) : cscale(s_py[slot][W], 0.5f);
+        const float2 ux = cmul(gp2, pyB);
+        ure[M] = ux.x;
+        uim[M] = ux.y;
+      } else {
+        u = cmul(gp2, s_py[slot][2 * m + h]);
+      }
+      ure[m] = u.x;
+      uim[m] = u.y;
+    });
+    // Nyquist column, row l: h = 1, halved for the factor 2 in GN, and the
+    // weight 1/2 of each of the nu = +-1/2 representatives
+    const float2 gamN = cscale(cmulc(p.psf_nyq[l], GN), 0.25f / ((float)W * (float)W));
+    const bool corner = (l == W / 2);
+    const float2 pyA = corner ? make_float2(0.5f * cy, 0.5f * sy) : make_float2(cy, sy);
+    const float2 pyB = corner ? make_float2(0.5f * cym, 0.5f * sym) : make_float2(0.f, 0.f);
+    const float2 eM = make_float2(cxh, sxh), eP = make_float2(cxh, -sxh);
+    const float2 u1 = cmul(cmul(gamN, eM), pyA), u2 = cmul(cmul(gamN, eP), pyA);
+    const float2 u3 = cmul(cmul(gamN, eM), pyB), u4 = cmul(cmul(gamN, eP), pyB);
+    ure[M + 1] = u1.x; uim[M + 1] = u1.y;  // (+1/2, omN)
+    ure[M + 2] = u2.x; uim[M + 2] = u2.y;  // (-1/2, omN)
+    ure[M + 3] = u3.x; uim[M + 3] = u3.y;  // (+1/2, -1/2)
+    ure[M + 4] = u4.x; uim[M + 4] = u4.y;  // (-1/2, -1/2)
+  }
+
+  // ------------------------------------------------------------ component loop
+  float ax = 0.f, ay = 0.f, a11 = 0.f, a12 = 0.f, a22 = 0.f;
+  for (int k = 0; k < kKmax; ++k) s_pk[slot][k][l] = 0.f;
+  static_for<0, (NP + C::PB - 1) / C::PB>([&](auto bb) {
+    constexpr int b0 = decltype(bb)::value * C::PB;
+    constexpr int nb = (NP - b0) < C::PB ? (NP - b0) : C::PB;
+    float gq[nb], S[nb], S1[nb];
+    static_for<0, nb>([&](auto jj) {
+      constexpr int j = decltype(jj)::value;
+      float n_, o_;
+      point(std::integral_constant<int, b0 + j>{}, n_, o_);
+      gq[j] = kQ * fmaf(G.b11 * n_, n_, fmaf(2.f * G.b12 * n_, o_, G.b22 * o_ * o_));
+      S[j] = 0.f;
+      S1[j] = 0.f;
+    });
+    for (int k = 0; k < kloop; ++k) {
+      const float v = var[k];
+      const float A = (k < G.K) ? amp[k] : 0.f;
+      // p_k is needed when w_k > 0 (amplitude and ramp terms); w_k = 0 means n_k <= 3,
+      // where the ramp slope vanishes too
+      const float wa = route_weight<W>(v * trB, p.flags) * A;
+      if (wa == 0.f) continue;
+      const float wav = wa * v;
+      float pk = 0.f;
+      static_for<0, nb>([&](auto jj) {
+        constexpr int j = decltype(jj)::value;
+        const float e = __builtin_amdgcn_exp2f(v * gq[j]);
+        S[j] = fmaf(wa, e, S[j]);
+        S1[j] = fmaf(wav, e, S1[j]);
+        pk = fmaf(ure[b0 + j], e, pk);
+      });
+      s_pk[slot][k][l] += pk;
+    }
+    static_for<0, nb>([&](auto jj) {
+      constexpr int j = decltype(jj)::value;
+      float n_, o_;
+      point(std::integral_constant<int, b0 + j>{}, n_, o_);
+      const float si = S[j] * uim[b0 + j];
+      const float r1 = S1[j] * ure[b0 + j];
+      ax = fmaf(n_, si, ax);
+      ay = fmaf(o_, si, ay);
+      a11 = fmaf(n_ * n_, r1, a11);
+      a12 = fmaf(n_ * o_, r1, a12);
+      a22 = fmaf(o_ * o_, r1, a22);
+    });
+  });
+  ax = seg_sum<W>(ax, s_x2);
+  ay = seg_sum<W>(ay, s_x2);
+  a11 = seg_sum<W>(a11, s_x2);
+  a12 = seg_sum<W>(a12, s_x2);
+  a22 = seg_sum<W>(a22, s_x2);
+  __syncthreads();
+  // p_k = sum over the stamp's lanes, fixed order; lane k of the stamp sums row k
+  if (l < kKmax) {
+    float acc = 0.f;
+    for (int i = 0; i < W; ++i) acc += s_pk[slot][l][i];
+    s_pk[slot][l][0] = acc;
+  }
+  __syncthreads();
+
+  // ------------------------------------------------------------ chain rule (lane 0)
+  if (l == 0 && live) {
+    constexpr float kPi = 3.14159265358979f;
+    const float F = G.flux;
+    const float pamp = p.pg[5];
+    float dxs = 2.f * kPi * F * ax;
+    float dys = 2.f * kPi * F * ay;
+    float dF = 0.f;
+    float L11 = -2.f * kPi * kPi * F * a11;
+    float L12 = -4.f * kPi * kPi * F * a12;
+    float L22 = -2.f * kPi * kPi * F * a22;
+    float* ap = amp_part + gidx * kKmax;
+    for (int k = 0; k < kKmax; ++k) {
+      if (k >= G.K) {
+        ap[k] = 0.f;
+        continue;
+      }
+      const float v = var[k];
+      const float A = amp[k];
+      const float tr = v * trB;
+      const float w = route_weight<W>(tr, p.flags);
+      const float n = (0.5f * (float)W) * __builtin_amdgcn_rsqf(tr);
+      const float pk = s_pk[slot][k][0];
+      float g0 = 0.f;
+      if (rmask & (1u << k)) {
+        const float* R = s_racc[slot][k];
+        g0 = R[0];
+        const float sxx = fmaf(v, G.b11, p.pg[2]);
+        const float sxy = fmaf(v, G.b12, p.pg[3]);
+        const float syy = fmaf(v, G.b22, p.pg[4]);
+        const float det = fmaf(sxx, syy, -(sxy * sxy));
+        const float ixx = syy / det, ixy = -sxy / det, iyy = sxx / det;
+        const float rk = (1.f - w) * F * A * pamp;
+        dxs = fmaf(rk, R[1], dxs);
+        dys = fmaf(rk, R[2], dys);
+        L11 = fmaf(0.5f * rk * v, R[3] - ixx * R[0], L11);
+        L12 = fmaf(rk * v, R[4] - ixy * R[0], L12);
+        L22 = fmaf(0.5f * rk * v, R[5] - iyy * R[0], L22);
+      }
+      dF += A * (w * pk + (1.f - w) * pamp * g0);
+      ap[k] = G.ok ? F * (w * pk + (1.f - w) * pamp * g0) : 0.f;
+      // smooth routing: dL/dw_k * dw/dn * dn/d(b11 or b22)
+      const float dLdw = F * A * (pk - pamp * g0);
+      const float dn = -0.5f * n / trB;
+      const float t = route_slope<W>(n, p.flags) * dLdw * dn;
+      L11 += t;
+      L22 += t;
+    }
+    // B = M C0 M^T  ->  dL/dC0 = M^T (dL/dB) M with symmetric dL/dB
+    const float m00 = p.cdinv[0], m01 = p.cdinv[1], m10 = p.cdinv[2], m11 = p.cdinv[3];
+    const float g11 = L11, g12 = 0.5f * L12, g22 = L22;
+    // T = (dL/dB) M
+    const float t00 = g11 * m00 + g12 * m10, t01 = g11 * m01 + g12 * m11;
+    const float t10 = g12 * m00 + g22 * m10, t11 = g12 * m01 + g22 * m11;
+    const float c11g = m00 * t00 + m10 * t10;
+    const float c12g = 2.f * (m00 * t01 + m10 * t11);
+    const float c22g = m01 * t01 + m11 * t11;
+    // C0 = s [[1 + e^2 - 2 e1, 2 e2], [2 e2, 1 + e^2 + 2 e1]], s = r_e^2 / (1 + e)^2
+    const float re = p.r_e[gidx], e1 = p.e1[gidx], e2 = p.e2[gidx];
+    const float esq = e1 * e1 + e2 * e2, e = sqrtf(esq);
+    const float s = re * re / ((1.f + e) * (1.f + e));
+    const float c11 = s * (1.f + esq - 2.f * e1), c12 = 2.f * s * e2, c22 = s * (1.f + esq + 2.f * e1);
+    const float dlogre = 2.f * (c11g * c11 + c12g * c12 + c22g * c22);
+    float de1 = 0.f, de2 = 0.f;
+    if (e > 0.f) {
+      const float ds1 = -2.f * s / (1.f + e) * (e1 / e), ds2 = -2.f * s / (1.f + e) * (e2 / e);
+      const float a11e = 1.f + esq - 2.f * e1, a22e = 1.f + esq + 2.f * e1;
+      de1 = c11g * (ds1 * a11e + s * (2.f * e1 - 2.f)) + c12g * (ds1 * 2.f * e2) +
+            c22g * (ds1 * a22e + s * (2.f * e1 + 2.f));
+      de2 = c11g * (ds2 * a11e + s * 2.f * e2) + c12g * (ds2 * 2.f * e2 + 2.f * s) +
+            c22g * (ds2 * a22e + s * 2.f * e2);
+    }
+    float* gpo = grad_params + gidx * 6;
+    gpo[0] = dxs;
+    gpo[1] = dys;
+    gpo[2] = dF;
+    gpo[3] = dlogre;
+    gpo[4] = de1;
+    gpo[5] = de2;
+  }
+}
+
+// grad_amp[t][k] += sum over galaxies i with table t of amp_part[i][k], in
+// index order within fixed 256-wide strides, then a fixed tree.
+__global__ void amp_grad_reduce(const float* __restrict__ amp_part, const int32_t* __restrict__ mix_id,
+                                int64_t n, int n_tables, float* __restrict__ grad_amp) {
+  const int t = blockIdx.x / kKmax, k = blockIdx.x % kKmax;
+  __shared__ float s[256];
+  float acc = 0.f;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    const int ti = mix_id ? mix_id[i] : 0;
+    if (ti == t) acc += amp_part[i * kKmax + k];
+  }
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) grad_amp[t * kKmax + k] += s[0];
+}
+
+template <int W>
+static hipError_t launch_bwd_small(const RenderArgs& args, const float* gout, float* grad_params,
+                                   float* amp_part, hipStream_t stream) {
+  using C = BwdCfg<W>;
+  constexpr int64_t kMaxBlocks = 1 << 30;
+  RenderArgs p = args;
+  int64_t done = 0;
+  while (done < args.n) {
+    const int64_t chunk = std::min<int64_t>(args.n - done, kMaxBlocks * C::SPB);
+    p.x = args.x + done;
+    p.y = args.y + done;
+    p.flux = args.flux + done;
+    p.r_e = args.r_e + done;
+    p.e1 = args.e1 + done;
+    p.e2 = args.e2 + done;
+    p.mix_id = args.mix_id ? args.mix_id + done : nullptr;
+    p.n = chunk;
+    const unsigned blocks = (unsigned)((chunk + C::SPB - 1) / C::SPB);
+    hipLaunchKernelGGL(render_bwd_small_kernel<W>, dim3(blocks), dim3(C::BLOCK), 0, stream, p,
+                       gout + done * (int64_t)W * W, grad_params + done * 6, amp_part + done * kKmax);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    done += chunk;
+  }
+  return hipSuccess;
+}
+
+}  // namespace gfc
+
+using namespace gfc;
 
 extern "C" {
-size_t gfc_backward_workspace_bytes(int64_t n) { return n > 0 ? (size_t)n * 64 : 0; }
-gfc_status gfc_render_stamps_backward(gfc_ctx*, gfc_psf*, const gfc_mix*, const gfc_galaxies*, int64_t,
-                                      int, unsigned, const float*, float*, float*, void*, void*) {
-  return gfc::fail(GFC_EUNSUPPORTED, "adjoint not built yet");
+
+size_t gfc_backward_workspace_bytes(int64_t n) {
+  return n > 0 ? (size_t)n * kKmax * sizeof(float) + 6 * sizeof(float) * (size_t)n : 0;
 }
+
+gfc_status gfc_render_stamps_backward(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix* mix, const gfc_galaxies* gal,
+                                      int64_t n, int W, unsigned flags, const float* grad_out,
+                                      float* grad_params, float* grad_amp, void* workspace,
+                                      void* hip_stream) {
+  RenderArgs a;
+  gfc_status st = fill_render_args(ctx, psf, mix, gal, n, W, flags, &a);
+  if (st != GFC_OK) return st;
+  if (n == 0) return GFC_OK;
+  if (!grad_out) return fail(GFC_EINVAL, "null upstream gradient");
+  if (W == 256) return fail(GFC_EUNSUPPORTED, "the adjoint supports W = 16, 32, 64 and 128");
+  DeviceGuard guard(ctx->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  const PsfSpectrum* spec = nullptr;
+  st = psf_cache(psf, W, s, &spec);
+  if (st != GFC_OK) return st;
+  a.psf_main = spec->main_cols;
+  a.psf_nyq = spec->nyq_col;
+  float* ws = static_cast<float*>(workspace);
+  bool own = false;
+  hipError_t e = hipSuccess;
+  if (!ws) {
+    e = hipMallocAsync((void**)&ws, gfc_backward_workspace_bytes(n), s);
+    if (e != hipSuccess) return fail(GFC_ENOMEM, "backward workspace allocation failed");
+    own = true;
+  }
+  float* amp_part = ws;
+  float* gp = grad_params ? grad_params : ws + (size_t)n * kKmax;
+  switch (W) {
+    case 16: e = launch_bwd_small<16>(a, grad_out, gp, amp_part, s); break;
+    case 32: e = launch_bwd_small<32>(a, grad_out, gp, amp_part, s); break;
+    case 64: e = launch_bwd_small<64>(a, grad_out, gp, amp_part, s); break;
+    case 128: e = launch_bwd_small<128>(a, grad_out, gp, amp_part, s); break;
+  }
+  if (e == hipSuccess && grad_amp) {
+    hipLaunchKernelGGL(amp_grad_reduce, dim3(mix->n_tables * kKmax), dim3(256), 0, s, amp_part,
+                       gal->mix_id, n, mix->n_tables, grad_amp);
+    e = hipGetLastError();
+  }
+  if (own) {
+    hipError_t e2 = hipFreeAsync(ws, s);
+    if (e == hipSuccess) e = e2;
+  }
+  if (e != hipSuccess) return hip_fail(e, "backward launch");
+  return GFC_OK;
 }
+
+}  // extern "C"

@@ -1,0 +1,194 @@
+"""GPU parity of the adjoint (gfc_render_stamps_backward, through the C ABI)
+against the FP64 derivative oracle, which itself is pinned to central finite
+differences on the CPU (tests/test_oracle_grad.py).
+
+Bar: for each parameter, |gpu - oracle| <= 1e-4 |oracle| + 1e-5 rms(oracle),
+where rms is over the galaxies of the case (the second term covers gradients
+that cancel to nearly zero, whose float32 rounding is set by the size of the
+summed terms, not by the result)."""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle as o
+import workloads as wl
+from gpu_helpers import lib_objects
+from oracle.grad import PARAMS
+
+pytestmark = pytest.mark.gpu
+
+RTOL, ATOL_RMS = 1e-4, 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2012_15797_amd as gfc
+    return gfc.Context.default(0)
+
+
+def oracle_grads(cfg, gal, g, flags=0, cd=None):
+    """Per-galaxy dL/d(x, y, flux, log r_e, e1, e2) and per-table amplitude
+    sums from the FP64 analytic Jacobian, with the float32 inputs the GPU saw."""
+    mix = cfg["mix"].as_f32()
+    P = np.asarray(cfg["psf"], np.float32).astype(np.float64)
+    gauss = cfg.get("psf_gauss")
+    gauss = o.psf_gauss_moments(P) if gauss is None else gauss
+    cache = {}
+    gp = np.zeros((len(gal), 6))
+    ga = np.zeros((mix.n_tables, 16))
+    for i in range(len(gal)):
+        p = gal.params(i)
+        W = p["W"]
+        if W not in cache:
+            cache[W] = o.psf_spectrum(P, W)
+        amp, var = mix.table(p["mix_id"])
+        _, J = o.render_stamp_jacobian(cache[W], gauss, amp, var, p["x"], p["y"], p["flux"], p["r_e"],
+                                       p["e1"], p["e2"], W, flags, cd)
+        lg = o.loss_gradient(np.asarray(g[i], np.float64), J)
+        gp[i] = [lg[k] for k in PARAMS]
+        ga[p["mix_id"], : len(amp)] += lg["amp"]
+    return gp, ga
+
+
+def gpu_grads(ctx, psf, mix, gal, W, g, flags=0, cd=None):
+    import torch
+    import paper_2012_15797_amd as gfc
+
+    gt = torch.as_tensor(np.ascontiguousarray(g, np.float32)).cuda()
+    gp, ga = gfc.gfc_render_stamps_backward(ctx, psf, mix, gal.x, gal.y, gal.flux, gal.r_e, gal.e1,
+                                            gal.e2, W, gt, mix_id=gal.mix_id, flags=flags, cd=cd)
+    torch.cuda.synchronize()
+    return gp.cpu().numpy().astype(np.float64), ga.cpu().numpy().astype(np.float64)
+
+
+def assert_close(gpu, ref, what):
+    ref = np.asarray(ref, np.float64)
+    rms = np.sqrt(np.mean(ref**2, axis=0, keepdims=True))
+    bound = np.broadcast_to(RTOL * np.abs(ref) + ATOL_RMS * rms, ref.shape)
+    err = np.abs(gpu - ref)
+    bad = err > bound
+    if bad.any():
+        i = tuple(np.argwhere(bad)[0])
+        worst = float((err / np.maximum(bound, 1e-300)).max())
+        raise AssertionError(f"{what}: {int(bad.sum())} of {bad.size} out of tolerance (worst {worst:.2f}x "
+                             f"the bound); first {i}: gpu {gpu[i]:.6e} oracle {ref[i]:.6e} bound {bound[i]:.3e}")
+
+
+@pytest.mark.parametrize("W", [16, 32, 64, 128])
+def test_backward_each_size(ctx, W):
+    rng = np.random.Generator(np.random.PCG64(300 + W))
+    cfg = wl.config2(10)
+    n = 40 if W < 128 else 12
+    gal = wl.draw_galaxies(rng, n, W, (np.arange(n) % 2).astype(np.int32), r_e_range=(0.4, W / 5.0))
+    g = rng.standard_normal((n, W, W)).astype(np.float32)
+    psf, mix = lib_objects(ctx, cfg)
+    gp, ga = gpu_grads(ctx, psf, mix, gal, W, g)
+    rp, ra = oracle_grads(cfg, gal, g)
+    assert_close(gp, rp, f"params W={W}")
+    assert_close(ga, ra, f"amplitudes W={W}")
+    psf.close(); mix.close()
+
+
+@pytest.mark.parametrize("flags", [1, 2, 4])
+def test_backward_routing_flags(ctx, flags):
+    rng = np.random.Generator(np.random.PCG64(400 + flags))
+    cfg = wl.config_metric(10)
+    W, n = 32, 30
+    gal = wl.draw_galaxies(rng, n, W, 0, r_e_range=(0.4, 6.0))
+    g = rng.standard_normal((n, W, W)).astype(np.float32)
+    psf, mix = lib_objects(ctx, cfg)
+    gp, ga = gpu_grads(ctx, psf, mix, gal, W, g, flags=flags)
+    rp, ra = oracle_grads(cfg, gal, g, flags=flags)
+    assert_close(gp, rp, f"params flags={flags}")
+    assert_close(ga, ra, f"amplitudes flags={flags}")
+    psf.close(); mix.close()
+
+
+def test_backward_fit_workload(ctx):
+    """The differentiation workload: DEV8, 64x64, upstream gradient
+    (I - T) / sigma^2 with T = render at perturbed parameters plus noise of
+    0.01 x peak; 40 galaxies."""
+    cfg = wl.config5(40)
+    gal, tgt = cfg["gal"], cfg["target_gal"]
+    idx = list(range(len(gal)))
+    I = np.stack(o.render_batch(cfg["psf"].astype(np.float64), cfg["mix"].as_f32(), gal, idx=idx))
+    T = np.stack(o.render_batch(cfg["psf"].astype(np.float64), cfg["mix"].as_f32(), tgt, idx=idx))
+    peak = np.abs(T).max(axis=(1, 2), keepdims=True)
+    sigma = 0.01 * peak
+    T = T + sigma * wl.generate.noise_field(cfg["noise_seed"], len(gal), 64)
+    g = ((I - T) / sigma**2).astype(np.float32)
+    psf, mix = lib_objects(ctx, cfg)
+    gp, ga = gpu_grads(ctx, psf, mix, gal, 64, g)
+    rp, ra = oracle_grads(cfg, gal, g)
+    assert_close(gp, rp, "params fit workload")
+    assert_close(ga, ra, "amplitudes fit workload")
+    psf.close(); mix.close()
+
+
+def test_backward_cd_matrix(ctx):
+    rng = np.random.Generator(np.random.PCG64(500))
+    cfg = wl.config_metric(10)
+    W, n = 32, 20
+    gal = wl.draw_galaxies(rng, n, W, 0, r_e_range=(0.4, 6.0))
+    g = rng.standard_normal((n, W, W)).astype(np.float32)
+    cd = np.array([0.9, 0.15, -0.2, 1.1], np.float32)
+    psf, mix = lib_objects(ctx, cfg)
+    gp, ga = gpu_grads(ctx, psf, mix, gal, W, g, cd=cd)
+    rp, ra = oracle_grads(cfg, gal, g, cd=cd.astype(np.float64))
+    assert_close(gp, rp, "params cd")
+    assert_close(ga, ra, "amplitudes cd")
+    psf.close(); mix.close()
+
+
+def test_backward_deterministic_and_accumulating(ctx):
+    import torch
+    import paper_2012_15797_amd as gfc
+
+    rng = np.random.Generator(np.random.PCG64(600))
+    cfg = wl.config_metric(10)
+    W, n = 64, 300
+    gal = wl.draw_galaxies(rng, n, W, 0)
+    g = torch.as_tensor(rng.standard_normal((n, W, W)).astype(np.float32)).cuda()
+    psf, mix = lib_objects(ctx, cfg)
+    args = (ctx, psf, mix, gal.x, gal.y, gal.flux, gal.r_e, gal.e1, gal.e2, W, g)
+    gp1, ga1 = gfc.gfc_render_stamps_backward(*args)
+    gp2, ga2 = gfc.gfc_render_stamps_backward(*args)
+    assert torch.equal(gp1, gp2) and torch.equal(ga1, ga2)
+    acc = torch.zeros_like(ga1)
+    gfc.gfc_render_stamps_backward(*args, grad_amp=acc)
+    gfc.gfc_render_stamps_backward(*args, grad_amp=acc)
+    torch.cuda.synchronize()
+    assert torch.allclose(acc, 2 * ga1, rtol=1e-6, atol=0)
+    psf.close(); mix.close()
+
+
+def test_autograd_function_matches_adjoint(ctx):
+    """torch.autograd through RenderStamps gives the library adjoint, with the
+    log r_e chain applied (dL/dr_e = dL/dlog r_e / r_e) and amplitude
+    gradients for a torch-held amplitude table."""
+    import torch
+    import paper_2012_15797_amd as gfc
+
+    rng = np.random.Generator(np.random.PCG64(700))
+    cfg = wl.config_metric(10)
+    W, n = 32, 25
+    gal = wl.draw_galaxies(rng, n, W, 0, r_e_range=(0.5, 5.0))
+    psf, mix = lib_objects(ctx, cfg)
+    dev = torch.device("cuda")
+    t = lambda a: torch.tensor(a, device=dev, requires_grad=True)
+    x, y, fl, re, e1, e2 = map(t, (gal.x, gal.y, gal.flux, gal.r_e, gal.e1, gal.e2))
+    amp = torch.tensor(cfg["mix"].as_f32().amp.astype(np.float32), device=dev, requires_grad=True)
+    g = torch.as_tensor(rng.standard_normal((n, W, W)).astype(np.float32), device=dev)
+    out = gfc.render(psf, mix, x, y, fl, re, e1, e2, W, amp=amp)
+    (out * g).sum().backward()
+    gp, ga = gfc.gfc_render_stamps_backward(ctx, psf, mix, gal.x, gal.y, gal.flux, gal.r_e, gal.e1,
+                                            gal.e2, W, g)
+    torch.cuda.synchronize()
+    for i, tt in enumerate((x, y, fl)):
+        assert torch.allclose(tt.grad, gp[:, i])
+    assert torch.allclose(re.grad, gp[:, 3] / re.detach())
+    assert torch.allclose(e1.grad, gp[:, 4]) and torch.allclose(e2.grad, gp[:, 5])
+    assert torch.allclose(amp.grad, ga)
+    psf.close(); mix.close()
