@@ -147,6 +147,8 @@ def main():
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=3.0,
+                    help="length of the Poisson request trace replayed against the server (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (for scaling HBM counters)")
     args = ap.parse_args()
@@ -238,6 +240,12 @@ def main():
         plain = plain_per_request(gfc, ctx, psf, mix, gal, W, dev)
         log(f"plain per-request launches: {plain['value']:.3e} stamps/s over {plain['requests']} requests")
 
+    serving = None
+    if args.serve_seconds > 0:
+        serving = serving_benchmark(gfc, ctx, args.serve_seconds)
+        log(f"serving: batched p50 {serving['batched']['p50_ms']} ms p99 {serving['batched']['p99_ms']} ms; "
+            f"plain p50 {serving['plain']['p50_ms']} ms p99 {serving['plain']['p99_ms']} ms")
+
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
@@ -257,10 +265,32 @@ def main():
                     routing="hybrid (smoothstep ramp n in [3,4])",
                     mean_K_F=round(float(kf.mean()), 3), mean_K_R=round(float(kr.mean()), 3)),
         roofline=roofline, cpu_baseline=cpu, parity=parity,
-        plain=plain, psf_cache_fill_ms=round(psf_cache_ms, 3),
+        plain=plain, serving=serving, psf_cache_fill_ms=round(psf_cache_ms, 3),
         kernel_ms=dict(mean=round(avg_kern_ms, 4), min=round(min(kern_ms), 4), max=round(max(kern_ms), 4)),
     )
     print(json.dumps(rec), flush=True)
+
+
+def serving_benchmark(gfc, ctx, seconds):
+    """Open-loop replay of the 64x64 serving trace (Poisson arrivals at
+    2,000 requests/s, 1..4096 galaxies per request, DEV8, the throughput
+    workload's PSF) against the continuous-batching server and against the
+    plain mode (one launch per request, FIFO on one stream), with the same
+    32 GB device-memory budget."""
+    from paper_2012_15797_amd.serving import Server, replay_trace
+
+    tr = wl.config4_trace(duration_s=seconds, rate_hz=2000.0, restricted=True)
+    psfs = [gfc.Psf(ctx, p) for p in tr["psfs"]]
+    mix = gfc.Mixture.from_workload(ctx, tr["mix"].as_f32())
+    for p in psfs:
+        p.prepare(64)
+    out = dict(trace=f"{len(tr['requests'])} requests over {seconds:.1f} s, Poisson 2000/s, "
+                     "1..4096 galaxies log-uniform, 64x64, DEV8, one PSF, budget 32 GB")
+    for name, streams, max_batch in (("batched", 2, 1 << 16), ("plain", 1, 0)):
+        srv = Server(ctx, mem_budget_bytes=32 << 30, n_streams=streams, max_batch_stamps=max_batch)
+        out[name] = replay_trace(srv, tr["requests"], psfs, mix)
+        srv.close()
+    return out
 
 
 def plain_per_request(gfc, ctx, psf, mix, gal, W, dev, seed=77):

@@ -186,8 +186,10 @@ typedef struct {
 } gfc_request;
 
 /* mem_budget_bytes: device bytes the server may hold for admitted requests
- * (outputs + parameters); max_batch_stamps: most stamps fused into one
- * launch; n_streams: concurrent launch streams (1..8). */
+ * (outputs + parameters: n * (4 W^2 + 28) bytes each); max_batch_stamps:
+ * most stamps fused into one launch (<= 0: one launch per request, the plain
+ * mode); n_streams: concurrent launch streams (1..8).  The policy is that of
+ * the scheduling core below.  A background thread launches and reaps. */
 gfc_status gfc_server_create(gfc_ctx* ctx, size_t mem_budget_bytes, int n_streams,
                              int64_t max_batch_stamps, gfc_server** out);
 /* Queues a request; returns at once with a ticket.  GFC_EREJECTED if the
@@ -201,6 +203,9 @@ gfc_status gfc_server_poll(gfc_server* srv, uint64_t ticket, int* done, const fl
 /* Blocks until the request completes or timeout_ms passes (< 0: forever). */
 gfc_status gfc_server_wait(gfc_server* srv, uint64_t ticket, int timeout_ms,
                            const float** out_dev);
+/* Copies a finished request's stamps (n*W*W float32) into dst (device),
+ * asynchronously on hip_stream.  GFC_EBUSY if the request is not done. */
+gfc_status gfc_server_copy(gfc_server* srv, uint64_t ticket, float* dst, void* hip_stream);
 /* Returns the request's device memory to the budget. */
 gfc_status gfc_server_release(gfc_server* srv, uint64_t ticket);
 /* Latency (submit -> completion) percentiles over completed requests, and
@@ -209,6 +214,47 @@ gfc_status gfc_server_stats(gfc_server* srv, double* p50_ms, double* p99_ms, dou
                             double* stamps_per_s, uint64_t* n_launches, uint64_t* n_done);
 /* Drains every queued request, then frees the server. */
 gfc_status gfc_server_destroy(gfc_server* srv);
+
+/* ------------------------------------------------- scheduling core (host) */
+/* The server's scheduler with the device replaced by caller callbacks, for
+ * driving and testing the policy without a GPU: strict-FIFO admission
+ * against the memory budget, batches of admitted requests that share a key
+ * (PSF, mixture, stamp size, flags) formed oldest-first up to
+ * max_batch_stamps (<= 0: one request per launch, the plain mode), at most
+ * one batch in flight per stream, latency = completion - submit on the
+ * callbacks' clock.  Nothing runs in the background: each gfc_sched_step()
+ * reaps completed batches, admits and launches. */
+typedef struct gfc_sched gfc_sched;
+typedef struct {
+  void* user;
+  double (*now)(void* user); /* seconds */
+  /* start batch `batch` of n_req requests (tickets[]) and n_stamps stamps on
+   * stream `stream`; return 0, or nonzero to fail the batch's requests */
+  int (*launch)(void* user, uint64_t batch, int stream, int n_req, const uint64_t* tickets,
+                int64_t n_stamps);
+  int (*poll)(void* user, uint64_t batch); /* 1 done, 0 running, < 0 failed */
+  void (*release)(void* user, uint64_t batch); /* its memory may be reused */
+} gfc_sched_executor;
+
+enum { GFC_REQ_PENDING = 0, GFC_REQ_ADMITTED = 1, GFC_REQ_LAUNCHED = 2, GFC_REQ_DONE = 3,
+       GFC_REQ_FAILED = 4 };
+
+gfc_status gfc_sched_create(const gfc_sched_executor* ex, size_t mem_budget_bytes, int n_streams,
+                            int64_t max_batch_stamps, gfc_sched** out);
+/* key: batching key; bytes: device bytes the request holds until released.
+ * GFC_EREJECTED if bytes > budget. */
+gfc_status gfc_sched_submit(gfc_sched* s, uint64_t key, int64_t n_stamps, size_t bytes,
+                            uint64_t* ticket);
+gfc_status gfc_sched_step(gfc_sched* s);
+/* state: one of GFC_REQ_*; batch: the batch it was launched in (0 before). */
+gfc_status gfc_sched_query(gfc_sched* s, uint64_t ticket, int* state, uint64_t* batch);
+/* GFC_EBUSY unless the request is done or failed. */
+gfc_status gfc_sched_release(gfc_sched* s, uint64_t ticket);
+/* bytes currently charged to admitted, unreleased requests */
+gfc_status gfc_sched_usage(gfc_sched* s, size_t* bytes_in_use, uint64_t* n_pending);
+gfc_status gfc_sched_stats(gfc_sched* s, double* p50_ms, double* p99_ms, double* max_ms,
+                           double* stamps_per_s, uint64_t* n_launches, uint64_t* n_done);
+gfc_status gfc_sched_destroy(gfc_sched* s);
 
 #ifdef __cplusplus
 }

@@ -82,11 +82,33 @@ PROTOTYPES = {
     "gfc_server_submit": (I32, [P, ctypes.POINTER(gfc_request), ctypes.POINTER(U64)]),
     "gfc_server_poll": (I32, [P, U64, ctypes.POINTER(I32), PP, ctypes.POINTER(I32)]),
     "gfc_server_wait": (I32, [P, U64, I32, PP]),
+    "gfc_server_copy": (I32, [P, U64, P, P]),
     "gfc_server_release": (I32, [P, U64]),
     "gfc_server_stats": (I32, [P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D),
                                ctypes.POINTER(D), ctypes.POINTER(U64), ctypes.POINTER(U64)]),
     "gfc_server_destroy": (I32, [P]),
+    "gfc_sched_create": (I32, [ctypes.c_void_p, ctypes.c_size_t, I32, I64, PP]),
+    "gfc_sched_submit": (I32, [P, U64, I64, ctypes.c_size_t, ctypes.POINTER(U64)]),
+    "gfc_sched_step": (I32, [P]),
+    "gfc_sched_query": (I32, [P, U64, ctypes.POINTER(I32), ctypes.POINTER(U64)]),
+    "gfc_sched_release": (I32, [P, U64]),
+    "gfc_sched_usage": (I32, [P, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(U64)]),
+    "gfc_sched_stats": (I32, [P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D),
+                              ctypes.POINTER(D), ctypes.POINTER(U64), ctypes.POINTER(U64)]),
+    "gfc_sched_destroy": (I32, [P]),
 }
+
+# gfc_sched_executor callbacks
+SCHED_NOW = ctypes.CFUNCTYPE(ctypes.c_double, ctypes.c_void_p)
+SCHED_LAUNCH = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
+                                ctypes.POINTER(ctypes.c_uint64), ctypes.c_int64)
+SCHED_POLL = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64)
+SCHED_RELEASE = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_uint64)
+
+
+class gfc_sched_executor(ctypes.Structure):
+    _fields_ = [("user", ctypes.c_void_p), ("now", SCHED_NOW), ("launch", SCHED_LAUNCH),
+                ("poll", SCHED_POLL), ("release", SCHED_RELEASE)]
 
 _lib = None
 

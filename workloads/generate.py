@@ -265,15 +265,25 @@ def config3(n=20_000):
     return dict(name="large-128-256", mix=mix, psf=psf, psf_gauss=gauss, gal=gal, flags=0)
 
 
-def config4_trace(duration_s=60.0, rate_hz=2000.0, n_psf=64, seed_offset=4):
+def config4_trace(duration_s=60.0, rate_hz=2000.0, n_psf=64, seed_offset=4, restricted=False):
     """Serving trace: Poisson arrivals; each request has 1..4096 galaxies
     (log-uniform), one of n_psf resident PSFs (Moffat+halo, FWHM uniform
     3..7 px) and a stamp size from {16, 32, 64, 128, 256}.  Galaxy parameters
-    are drawn per request with the batched-render distributions."""
+    are drawn per request with the batched-render distributions.
+
+    restricted=True gives the variant tied to the throughput workload: every
+    request uses 64x64 stamps, the DEV8 table and the throughput workload's
+    Moffat+halo PSF."""
     rng = np.random.Generator(np.random.PCG64(SEED_BASE + seed_offset))
-    mix = mixture_set([exp6_table(rng), dev8_table(rng)])
-    fwhm = rng.uniform(3.0, 7.0, n_psf)
-    psfs = [psf_moffat_halo(64, fwhm=float(f)).astype(np.float32) for f in fwhm]
+    if restricted:
+        mix = mixture_set([dev8_table(np.random.Generator(np.random.PCG64(SEED_BASE + 2)))])
+        psfs = [_psf_b().astype(np.float32)]
+        sizes, tables = [64], [0]
+    else:
+        mix = mixture_set([exp6_table(rng), dev8_table(rng)])
+        fwhm = rng.uniform(3.0, 7.0, n_psf)
+        psfs = [psf_moffat_halo(64, fwhm=float(f)).astype(np.float32) for f in fwhm]
+        sizes, tables = [16, 32, 64, 128, 256], [0, 1]
     t = 0.0
     reqs = []
     while True:
@@ -281,11 +291,11 @@ def config4_trace(duration_s=60.0, rate_hz=2000.0, n_psf=64, seed_offset=4):
         if t >= duration_s:
             break
         n = int(min(4096, max(1, math.floor(_log_uniform(rng, 1.0, 4097.0, 1)[0]))))
-        W = int(rng.choice([16, 32, 64, 128, 256]))
-        p = int(rng.integers(0, n_psf))
-        gal = draw_galaxies(rng, n, W, int(rng.integers(0, 2)))
+        W = int(rng.choice(sizes))
+        p = int(rng.integers(0, len(psfs)))
+        gal = draw_galaxies(rng, n, W, int(rng.choice(tables)))
         reqs.append(dict(t=t, psf=p, W=W, gal=gal))
-    return dict(name="serving-trace", mix=mix, psfs=psfs, requests=reqs)
+    return dict(name="serving-trace" + ("-64" if restricted else ""), mix=mix, psfs=psfs, requests=reqs)
 
 
 def config5(n=10_000):
