@@ -149,6 +149,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="length of the Poisson request trace replayed against the server (0: skip)")
+    ap.add_argument("--no-other", action="store_true", help="skip the other-workload throughput table")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (for scaling HBM counters)")
     args = ap.parse_args()
@@ -243,8 +244,11 @@ def main():
     serving = None
     if args.serve_seconds > 0:
         serving = serving_benchmark(gfc, ctx, args.serve_seconds)
-        log(f"serving: batched p50 {serving['batched']['p50_ms']} ms p99 {serving['batched']['p99_ms']} ms; "
-            f"plain p50 {serving['plain']['p50_ms']} ms p99 {serving['plain']['p99_ms']} ms")
+
+    other = None
+    if not args.no_other:
+        other = size_throughput(gfc, ctx, dev)
+        log(f"other workloads: {other}")
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
@@ -265,7 +269,7 @@ def main():
                     routing="hybrid (smoothstep ramp n in [3,4])",
                     mean_K_F=round(float(kf.mean()), 3), mean_K_R=round(float(kr.mean()), 3)),
         roofline=roofline, cpu_baseline=cpu, parity=parity,
-        plain=plain, serving=serving, psf_cache_fill_ms=round(psf_cache_ms, 3),
+        plain=plain, serving=serving, other_workloads=other, psf_cache_fill_ms=round(psf_cache_ms, 3),
         kernel_ms=dict(mean=round(avg_kern_ms, 4), min=round(min(kern_ms), 4), max=round(max(kern_ms), 4)),
     )
     print(json.dumps(rec), flush=True)
@@ -279,18 +283,90 @@ def serving_benchmark(gfc, ctx, seconds):
     32 GB device-memory budget."""
     from paper_2012_15797_amd.serving import Server, replay_trace
 
-    tr = wl.config4_trace(duration_s=seconds, rate_hz=2000.0, restricted=True)
-    psfs = [gfc.Psf(ctx, p) for p in tr["psfs"]]
-    mix = gfc.Mixture.from_workload(ctx, tr["mix"].as_f32())
-    for p in psfs:
-        p.prepare(64)
-    out = dict(trace=f"{len(tr['requests'])} requests over {seconds:.1f} s, Poisson 2000/s, "
-                     "1..4096 galaxies log-uniform, 64x64, DEV8, one PSF, budget 32 GB")
-    for name, streams, max_batch in (("batched", 2, 1 << 16), ("plain", 1, 0)):
-        srv = Server(ctx, mem_budget_bytes=32 << 30, n_streams=streams, max_batch_stamps=max_batch)
-        out[name] = replay_trace(srv, tr["requests"], psfs, mix)
-        srv.close()
+    out = {}
+    for label, rate, secs, restricted in (("", 2000.0, seconds, True),
+                                          ("saturated_", 20000.0, min(seconds, 1.0), True),
+                                          ("mixed_sizes_", 2000.0, min(seconds, 1.0), False)):
+        tr = wl.config4_trace(duration_s=secs, rate_hz=rate, restricted=restricted)
+        psfs = [gfc.Psf(ctx, p) for p in tr["psfs"]]
+        mix = gfc.Mixture.from_workload(ctx, tr["mix"].as_f32())
+        for p in psfs:
+            for W in sorted({r["W"] for r in tr["requests"]}):
+                p.prepare(W)
+        what = ("64x64, DEV8, one PSF" if restricted else
+                "stamp sizes 16..256, EXP6/DEV8, 64 PSFs")
+        out[label + "trace"] = (f"{len(tr['requests'])} requests over {secs:.1f} s, Poisson {rate:.0f}/s, "
+                                f"1..4096 galaxies log-uniform, {what}, budget 32 GB")
+        for name, streams, max_batch in (("batched", 2, 1 << 16), ("plain", 1, 0)):
+            srv = Server(ctx, mem_budget_bytes=32 << 30, n_streams=streams, max_batch_stamps=max_batch)
+            out[label + name] = replay_trace(srv, tr["requests"], psfs, mix)
+            srv.close()
+            log(f"serving {label or 'nominal_'}{name}: {out[label + name]}")
+        for p in psfs:
+            p.close()
+        mix.close()
     return out
+
+
+def size_throughput(gfc, ctx, dev, reps=5):
+    """Forward stamps/s per stamp size on the mixed-size and large-galaxy
+    workloads (one launch per size bin), and the adjoint on the
+    differentiation workload."""
+    import torch
+
+    res = {}
+    for cname, cfg in (("mixed-32-64-128", wl.config2()), ("large-128-256", wl.config3())):
+        psf = gfc.Psf(ctx, cfg["psf"], cfg.get("psf_gauss"))
+        mix = gfc.Mixture.from_workload(ctx, cfg["mix"].as_f32())
+        g = cfg["gal"]
+        tot_ms, tot_n = 0.0, 0
+        for W in sorted(set(int(w) for w in g.W)):
+            sub = g.subset(np.nonzero(g.W == W)[0])
+            d = lambda a: torch.as_tensor(a).to(dev)
+            args = [d(a) for a in (sub.x, sub.y, sub.flux, sub.r_e, sub.e1, sub.e2)]
+            mid = d(sub.mix_id)
+            out = torch.empty((len(sub), W, W), dtype=torch.float32, device=dev)
+            psf.prepare(W)
+            gfc.gfc_render_stamps(ctx, psf, mix, *args, W, mix_id=mid, out=out)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                gfc.gfc_render_stamps(ctx, psf, mix, *args, W, mix_id=mid, out=out)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            res[f"{cname}/W{W}"] = dict(stamps=len(sub), ms=round(ms, 4), stamps_per_s=round(len(sub) / ms * 1e3, 1))
+            tot_ms += ms
+            tot_n += len(sub)
+            del out
+        res[cname] = dict(stamps=tot_n, ms=round(tot_ms, 4), stamps_per_s=round(tot_n / tot_ms * 1e3, 1))
+        psf.close()
+        mix.close()
+    # adjoint on the differentiation workload (upstream gradient: unit normal noise)
+    cfg = wl.config5()
+    g = cfg["gal"]
+    psf = gfc.Psf(ctx, cfg["psf"])
+    mix = gfc.Mixture.from_workload(ctx, cfg["mix"].as_f32())
+    d = lambda a: torch.as_tensor(a).to(dev)
+    args = [d(a) for a in (g.x, g.y, g.flux, g.r_e, g.e1, g.e2)]
+    go = torch.randn((len(g), 64, 64), device=dev, generator=torch.Generator(device=dev).manual_seed(5))
+    ws = torch.empty(gfc.gfc_backward_workspace_bytes(len(g)) // 4 + 1, dtype=torch.float32, device=dev)
+    gp = torch.empty((len(g), 6), dtype=torch.float32, device=dev)
+    ga = torch.zeros((1, 16), dtype=torch.float32, device=dev)
+    gfc.gfc_render_stamps_backward(ctx, psf, mix, *args, 64, go, grad_params=gp, grad_amp=ga, workspace=ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        gfc.gfc_render_stamps_backward(ctx, psf, mix, *args, 64, go, grad_params=gp, grad_amp=ga, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    res["backward-dev8-64x64-10k"] = dict(stamps=len(g), ms=round(ms, 4), stamps_per_s=round(len(g) / ms * 1e3, 1))
+    psf.close()
+    mix.close()
+    return res
 
 
 def plain_per_request(gfc, ctx, psf, mix, gal, W, dev, seed=77):

@@ -163,6 +163,15 @@ gfc_status gfc_ctx_create(int hip_device, gfc_ctx** out) {
     delete ctx;
     return fail(GFC_ENOMEM, "invalid-counter allocation failed");
   }
+  // Stream-ordered scratch (the W = 256 slab, the adjoint workspace, serving
+  // batches) comes from the device's default memory pool; keep freed blocks
+  // cached in it instead of returning them to the driver at every
+  // synchronisation, so repeated calls do not pay for fresh allocations.
+  hipMemPool_t pool = nullptr;
+  if (hipDeviceGetDefaultMemPool(&pool, hip_device) == hipSuccess && pool) {
+    uint64_t keep = UINT64_MAX;
+    hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+  }
   e = hipMemset(ctx->d_invalid, 0, sizeof(unsigned long long));
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {

@@ -268,9 +268,12 @@ class HipExecutor : public Executor {
   HipExecutor(gfc_ctx* ctx, int n_streams) : ctx_(ctx) {
     DeviceGuard g(ctx_->device);
     streams_.resize(std::max(1, n_streams), nullptr);
+    events_.resize(streams_.size(), nullptr);
     staging_.resize(streams_.size(), nullptr);
     staging_bytes_.resize(streams_.size(), 0);
     for (auto& s : streams_) hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    // one completion event per stream: a stream holds at most one batch in flight
+    for (auto& e : events_) hipEventCreateWithFlags(&e, hipEventDisableTiming);
   }
   ~HipExecutor() override {
     DeviceGuard g(ctx_->device);
@@ -280,6 +283,8 @@ class HipExecutor : public Executor {
     }
     for (auto p : staging_)
       if (p) hipHostFree(p);
+    for (auto e : events_)
+      if (e) hipEventDestroy(e);
   }
   double now() override {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -335,7 +340,7 @@ class HipExecutor : public Executor {
     a.psf_nyq = spec->nyq_col;
     a.out = dout;
     if (render_launch(a, W, s) != GFC_OK) return fail_batch(b);
-    if (hipEventCreateWithFlags(&b.event, hipEventDisableTiming) != hipSuccess) return fail_batch(b);
+    b.event = events_[b.stream];
     if (hipEventRecord(b.event, s) != hipSuccess) return fail_batch(b);
     for (Req* r : b.reqs) r->out_ptr = dout + r->offset * (int64_t)W * W;
     return 0;
@@ -350,7 +355,6 @@ class HipExecutor : public Executor {
   void release(Batch& b) override {
     DeviceGuard g(ctx_->device);
     if (b.mem) hipFreeAsync(b.mem, streams_[b.stream]);
-    if (b.event) hipEventDestroy(b.event);
     b.mem = nullptr;
     b.event = nullptr;
   }
@@ -362,6 +366,7 @@ class HipExecutor : public Executor {
   }
   gfc_ctx* ctx_;
   std::vector<hipStream_t> streams_;
+  std::vector<hipEvent_t> events_;
   std::vector<void*> staging_;
   std::vector<size_t> staging_bytes_;
 };

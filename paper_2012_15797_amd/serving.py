@@ -26,8 +26,9 @@ class Server:
         self.handle = h
         self._meta = {}
 
-    def submit(self, psf, mix, W, x, y, flux, r_e, e1, e2, mix_id=None, flags=0) -> int:
-        """Queues a request with host parameter arrays (copied); returns its ticket."""
+    @staticmethod
+    def prepare(psf, mix, W, x, y, flux, r_e, e1, e2, mix_id=None, flags=0):
+        """Marshals one request (host arrays) into a gfc_request, ready to submit."""
         arrs = [np.ascontiguousarray(a, np.float32) for a in (x, y, flux, r_e, e1, e2)]
         n = arrs[0].shape[0]
         q = gfc_request()
@@ -38,10 +39,18 @@ class Server:
         if mix_id is not None:
             mid = np.ascontiguousarray(mix_id, np.int32)
             q.mix_id = mid.ctypes.data
+        return (q, arrs, mid, n, int(W))
+
+    def submit_prepared(self, prepared) -> int:
+        q, _arrs, _mid, n, W = prepared
         t = ctypes.c_uint64()
         call("gfc_server_submit", self.handle, ctypes.byref(q), ctypes.byref(t))
-        self._meta[t.value] = (n, int(W))
+        self._meta[t.value] = (n, W)
         return t.value
+
+    def submit(self, psf, mix, W, x, y, flux, r_e, e1, e2, mix_id=None, flags=0) -> int:
+        """Queues a request with host parameter arrays (copied); returns its ticket."""
+        return self.submit_prepared(self.prepare(psf, mix, W, x, y, flux, r_e, e1, e2, mix_id, flags))
 
     def poll(self, ticket: int):
         done, st = ctypes.c_int(), ctypes.c_int()
@@ -164,9 +173,15 @@ def replay_trace(server, requests, psfs, mix, flags=0):
             except Exception as e:  # noqa: BLE001 - reported after the run
                 err.append(e)
 
+    prepared = []
+    stamps = 0
+    for r in requests:
+        g = r["gal"]
+        prepared.append(server.prepare(psfs[r["psf"]], mix, r["W"], g.x, g.y, g.flux, g.r_e, g.e1, g.e2,
+                                       mix_id=g.mix_id, flags=flags))
+        stamps += len(g)
     th = threading.Thread(target=waiter, daemon=True)
     th.start()
-    stamps = 0
     t0 = time.perf_counter()
     for i, r in enumerate(requests):
         target = t0 + r["t"]
@@ -176,11 +191,8 @@ def replay_trace(server, requests, psfs, mix, flags=0):
                 break
             if d > 5e-4:
                 time.sleep(d - 3e-4)
-        g = r["gal"]
         lag[i] = time.perf_counter() - target
-        tickets[i] = server.submit(psfs[r["psf"]], mix, r["W"], g.x, g.y, g.flux, g.r_e, g.e1, g.e2,
-                                   mix_id=g.mix_id, flags=flags)
-        stamps += len(g)
+        tickets[i] = server.submit_prepared(prepared[i])
         q.put(i)
     q.put(None)
     th.join()
