@@ -29,9 +29,11 @@ struct SmallCfg {
   static constexpr int M = W / 2;                // values per lane in the column phase
   static constexpr int BLOCK = W < 64 ? 64 : W;  // threads per workgroup
   static constexpr int SPB = BLOCK / W;          // stamps per workgroup
-  static constexpr int T1S = W + 1;              // float2 per LDS row (padding kills bank conflicts)
-  static constexpr int T1N = M * T1S;            // float2 per stamp; also W x (W+1) floats
-  static constexpr int CH = W <= 64 ? W : 32;    // output rows per chunk
+  // Both LDS transposes run in two passes over halves of the data, so a
+  // stamp needs half the LDS and more wavefronts fit on a CU.
+  static constexpr int T1S = W / 2 + 1;          // float2 per row: W/4 columns x 2 halves + pad
+  static constexpr int T1N = M * T1S;            // float2 per stamp; also (W/2) x (W+1) floats
+  static constexpr int HR = W / 2;               // rows of the store tile per pass
 };
 
 template <int W>
@@ -44,8 +46,8 @@ render_small_kernel(RenderArgs p) {
   __shared__ float2 s_py[C::SPB][W + 2];
   __shared__ float2 s_nyq[C::SPB][W];
 
-  const int l = threadIdx.x % W;
-  const int slot = threadIdx.x / W;
+  const int l = (C::SPB == 1) ? (int)threadIdx.x : (int)threadIdx.x % W;
+  const int slot = (C::SPB == 1) ? 0 : (int)threadIdx.x / W;  // keeps the stamp index scalar
   const int64_t stamp = (int64_t)blockIdx.x * C::SPB + slot;
   const bool live = stamp < p.n;
   Galaxy G = load_galaxy<W>(p, live ? stamp : p.n - 1);
@@ -87,11 +89,27 @@ render_small_kernel(RenderArgs p) {
   qn[2] = fmaf(-0.5f, fmaf(qd, -0.5f, qb), qa);  // (+1/2, -1/2)
   qn[3] = fmaf(-0.5f, fmaf(qd, -0.5f, -qb), qa); // (-1/2, -1/2)
 
+  // Component 0 initialises the sums (every table has one; with zero Fourier
+  // weight it contributes zeros), the rest accumulate.
   float S[M + 1];
-  float SN[4] = {0.f, 0.f, 0.f, 0.f};
-  static_for<0, M + 1>([&](auto mm) { S[decltype(mm)::value] = 0.f; });
+  float SN[4];
   unsigned rmask = 0;  // components with a real-space share
-  for (int k = 0; k < kloop; ++k) {
+  {
+    const float v = var[0];
+    const float A = amp[0];
+    const float w = route_weight<W>(v * trB, p.flags);
+    if (w < 1.f && A != 0.f) rmask = 1u;
+    const float wa = w * A;
+    static_for<0, M + 1>([&](auto mm) {
+      constexpr int m = decltype(mm)::value;
+      S[m] = wa * __builtin_amdgcn_exp2f(v * qv[m]);
+    });
+    static_for<0, 4>([&](auto jj) {
+      constexpr int j = decltype(jj)::value;
+      SN[j] = wa * __builtin_amdgcn_exp2f(v * qn[j]);
+    });
+  }
+  for (int k = 1; k < kloop; ++k) {
     const float v = var[k];
     const float A = (k < G.K) ? amp[k] : 0.f;
     const float w = route_weight<W>(v * trB, p.flags);
@@ -154,29 +172,37 @@ render_small_kernel(RenderArgs p) {
     });
   }
   fft<M, +1>(Z);
-  static_for<0, M>([&](auto jj) {
-    constexpr int j = decltype(jj)::value;
-    s_t1[slot][j * T1S + l] = Z[j];
-  });
-  __syncthreads();
 
   // ---------------------------------------------------------------- row phase
   constexpr int NC = W / 2;
+  constexpr int QC = W / 4;  // columns per transpose pass
   const int y = l;
   const int jr = y & (M - 1);
   const float2 tw = twiddle_rt<+1, W>(y);
   float2 X[NC + 1];
-  static_for<0, NC>([&](auto cc) {
-    constexpr int cI = decltype(cc)::value;
-    const float2 e0 = s_t1[slot][jr * T1S + 2 * cI];
-    const float2 e1 = s_t1[slot][jr * T1S + 2 * cI + 1];
-    const float2 v = cadd(e0, cmul(tw, e1));
-    if constexpr (cI == 0) {
-      X[0] = make_float2(v.x, 0.f);
-      X[NC] = make_float2(v.y, 0.f);
-    } else {
-      X[cI] = v;
+  static_for<0, 2>([&](auto pp) {
+    constexpr int pass = decltype(pp)::value;
+    if (c / QC == pass) {
+      static_for<0, M>([&](auto jj) {
+        constexpr int j = decltype(jj)::value;
+        s_t1[slot][j * T1S + (l - 2 * QC * pass)] = Z[j];
+      });
     }
+    __syncthreads();
+    static_for<0, QC>([&](auto cc) {
+      constexpr int cl = decltype(cc)::value;
+      constexpr int cI = pass * QC + cl;
+      const float2 e0 = s_t1[slot][jr * T1S + 2 * cl];
+      const float2 e1 = s_t1[slot][jr * T1S + 2 * cl + 1];
+      const float2 v = cadd(e0, cmul(tw, e1));
+      if constexpr (cI == 0) {
+        X[0] = make_float2(v.x, 0.f);
+        X[NC] = make_float2(v.y, 0.f);
+      } else {
+        X[cI] = v;
+      }
+    });
+    __syncthreads();
   });
   // complex-to-real: R[k] = (X[k] + conj X[W/2-k]) + i w^k (X[k] - conj X[W/2-k]),
   // w = exp(2 pi i / W).  Bins k and W/2-k share s = X[k] + conj X[W/2-k] and
@@ -191,27 +217,34 @@ render_small_kernel(RenderArgs p) {
     if constexpr (k != 0 && 2 * k != NC) R[NC - k] = make_float2(sum.x + t.y, t.x - sum.y);
   });
   fft<NC, +1>(R);
-  __syncthreads();  // every lane has read s_t1; reuse it as the W x (W+1) store tile
-  float* st = reinterpret_cast<float*>(&s_t1[slot][0]);
-  static_for<0, NC>([&](auto nn) {
-    constexpr int n = decltype(nn)::value;
-    st[y * (W + 1) + 2 * n] = R[n].x;
-    st[y * (W + 1) + 2 * n + 1] = R[n].y;
-  });
-  __syncthreads();
 
   // ---------------------------------------------------------------- real space + store
-  const float dx = (float)l - G.x0 - p.pg[0];
-  float* outp = p.out + (live ? stamp : 0) * (int64_t)(W * W);
   // Output pixel (Y, X = l) is pixel ((Y - ny) mod W, (X - nx) mod W) of the
-  // fractional-offset Fourier image: the integer shift is a cyclic roll.
+  // fractional-offset Fourier image: the integer shift is a cyclic roll.  Pass
+  // q stages source rows q W/2 .. q W/2 + W/2 - 1 in LDS; they land on output
+  // rows (q W/2 + r + ny) mod W.
+  float* st = reinterpret_cast<float*>(&s_t1[slot][0]);
+  const float dx = (float)l - G.x0 - p.pg[0];
+  const float dyc = -G.y0 - p.pg[1];
+  float* outp = p.out + (live ? stamp : 0) * (int64_t)(W * W);
   const int colsrc = (l - G.nx) & (W - 1);
-  for (int r0 = 0; r0 < W; r0 += C::CH) {
-    float val[C::CH];
-    static_for<0, C::CH>([&](auto rr) {
+  static_for<0, 2>([&](auto qq) {
+    constexpr int q = decltype(qq)::value;
+    if (y / C::HR == q) {
+      static_for<0, NC>([&](auto nn) {
+        constexpr int n = decltype(nn)::value;
+        st[(y - q * C::HR) * (W + 1) + 2 * n] = R[n].x;
+        st[(y - q * C::HR) * (W + 1) + 2 * n + 1] = R[n].y;
+      });
+    }
+    __syncthreads();
+    float val[C::HR];
+    static_for<0, C::HR>([&](auto rr) {
       constexpr int r = decltype(rr)::value;
-      val[r] = st[((r0 + r - G.ny) & (W - 1)) * (W + 1) + colsrc];
+      val[r] = st[r * (W + 1) + colsrc];
     });
+    const int ybase = (q * C::HR + G.ny) & (W - 1);  // output row of r = 0
+    const int rwrap = W - ybase;                      // rows r >= rwrap wrap to the top
     for (unsigned mk = rmask; mk != 0; mk &= mk - 1) {
       const int k = __builtin_ctz(mk);
       const float v = var[k];
@@ -225,20 +258,23 @@ render_small_kernel(RenderArgs p) {
       const float a0 = kHalfLog2e * (syy * rdet) * dx * dx;
       const float a1 = -2.f * kHalfLog2e * (sxy * rdet) * dx;
       const float a2 = kHalfLog2e * (sxx * rdet);
-      const float dy0 = (float)r0 - G.y0 - p.pg[1];
-      static_for<0, C::CH>([&](auto rr) {
+      const float dyb = (float)ybase + dyc;
+      const float dybw = dyb - (float)W;
+      static_for<0, C::HR>([&](auto rr) {
         constexpr int r = decltype(rr)::value;
-        const float dy = dy0 + (float)r;
+        const float dy = ((r >= rwrap) ? dybw : dyb) + (float)r;
         val[r] = fmaf(ampr, __builtin_amdgcn_exp2f(fmaf(dy, fmaf(a2, dy, a1), a0)), val[r]);
       });
     }
     if (live) {
-      static_for<0, C::CH>([&](auto rr) {
+      static_for<0, C::HR>([&](auto rr) {
         constexpr int r = decltype(rr)::value;
-        outp[(r0 + r) * W + l] = val[r];
+        float* rowp = outp + ((ybase + r) & (W - 1)) * W;  // uniform when one stamp per wavefront
+        rowp[l] = val[r];
       });
     }
-  }
+    __syncthreads();
+  });
   if (live && !G.ok && l == 0) atomicAdd(p.invalid, 1ull);
 }
 
