@@ -163,7 +163,9 @@ gfc_status gfc_render_stamps(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix* mix,
  * NULL.  At e = 0 the derivative w.r.t. (e1, e2) is taken as 0 (the profile
  * has a cone there).  workspace: device scratch of at least
  * gfc_backward_workspace_bytes(n) bytes, or NULL to let the library
- * allocate it per call.  Asynchronous on hip_stream. */
+ * allocate it per call.  W = 256 also takes a stream-ordered device slab of
+ * 256 KiB per stamp (at most 1024 stamps at a time) inside the call.
+ * Asynchronous on hip_stream. */
 size_t gfc_backward_workspace_bytes(int64_t n);
 gfc_status gfc_render_stamps_backward(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix* mix,
                                       const gfc_galaxies* gal, int64_t n, int W,

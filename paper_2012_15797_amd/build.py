@@ -30,6 +30,7 @@ SOURCES = [
     "render_fwd.hip",
     "render_large.hip",
     "render_bwd.hip",
+    "render_bwd_large.hip",
     "psf_fft.hip",
     "serve.cpp",
 ]

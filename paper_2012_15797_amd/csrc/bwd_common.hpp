@@ -1,0 +1,102 @@
+// Shared tail of the adjoint kernels: the chain rule from the frequency- and
+// pixel-domain sums of one stamp to d loss / d(x, y, flux, log r_e, e1, e2)
+// and the per-galaxy amplitude partials (Section 2, steps 3 and 4
+// differentiated).
+#pragma once
+
+#include "gfc_device.hpp"
+
+namespace gfc {
+
+// ax, ay, a11, a12, a22: stamp sums of the Fourier-path terms (see the adjoint
+// kernels); pk_sum[k * pk_stride]: per-component Fourier sums p_k;
+// racc[6 k + i]: per-component real-space sums (sum g N, g N z_x, g N z_y,
+// g N z_x^2, g N z_x z_y, g N z_y^2).
+template <int W>
+__device__ inline void bwd_chain_rule(const RenderArgs& p, const Galaxy& G, int64_t gidx, unsigned rmask,
+                                      float ax, float ay, float a11, float a12, float a22,
+                                      const float* pk_sum, int pk_stride, const float* racc,
+                                      float* grad_params, float* amp_part) {
+  const float* amp = p.amp + G.table * kKmax;
+  const float* var = p.var + G.table * kKmax;
+  const float trB = G.b11 + G.b22;
+  constexpr float kPi = 3.14159265358979f;
+  const float F = G.flux;
+  const float pamp = p.pg[5];
+  float dxs = 2.f * kPi * F * ax;
+  float dys = 2.f * kPi * F * ay;
+  float dF = 0.f;
+  float L11 = -2.f * kPi * kPi * F * a11;
+  float L12 = -4.f * kPi * kPi * F * a12;
+  float L22 = -2.f * kPi * kPi * F * a22;
+  float* ap = amp_part + gidx * kKmax;
+  for (int k = 0; k < kKmax; ++k) {
+    if (k >= G.K) {
+      ap[k] = 0.f;
+      continue;
+    }
+    const float v = var[k];
+    const float A = amp[k];
+    const float tr = v * trB;
+    const float w = route_weight<W>(tr, p.flags);
+    const float n = (0.5f * (float)W) * __builtin_amdgcn_rsqf(tr);
+    const float pk = pk_sum[k * pk_stride];
+    float g0 = 0.f;
+    if (rmask & (1u << k)) {
+      const float* R = racc + 6 * k;
+      g0 = R[0];
+      const float sxx = fmaf(v, G.b11, p.pg[2]);
+      const float sxy = fmaf(v, G.b12, p.pg[3]);
+      const float syy = fmaf(v, G.b22, p.pg[4]);
+      const float det = fmaf(sxx, syy, -(sxy * sxy));
+      const float ixx = syy / det, ixy = -sxy / det, iyy = sxx / det;
+      const float rk = (1.f - w) * F * A * pamp;
+      dxs = fmaf(rk, R[1], dxs);
+      dys = fmaf(rk, R[2], dys);
+      L11 = fmaf(0.5f * rk * v, R[3] - ixx * R[0], L11);
+      L12 = fmaf(rk * v, R[4] - ixy * R[0], L12);
+      L22 = fmaf(0.5f * rk * v, R[5] - iyy * R[0], L22);
+    }
+    dF += A * (w * pk + (1.f - w) * pamp * g0);
+    ap[k] = G.ok ? F * (w * pk + (1.f - w) * pamp * g0) : 0.f;
+    // smooth routing: dL/dw_k * dw/dn * dn/d(b11 or b22)
+    const float dLdw = F * A * (pk - pamp * g0);
+    const float dn = -0.5f * n / trB;
+    const float t = route_slope<W>(n, p.flags) * dLdw * dn;
+    L11 += t;
+    L22 += t;
+  }
+  // B = M C0 M^T  ->  dL/dC0 = M^T (dL/dB) M with symmetric dL/dB
+  const float m00 = p.cdinv[0], m01 = p.cdinv[1], m10 = p.cdinv[2], m11 = p.cdinv[3];
+  const float g11 = L11, g12 = 0.5f * L12, g22 = L22;
+  // T = (dL/dB) M
+  const float t00 = g11 * m00 + g12 * m10, t01 = g11 * m01 + g12 * m11;
+  const float t10 = g12 * m00 + g22 * m10, t11 = g12 * m01 + g22 * m11;
+  const float c11g = m00 * t00 + m10 * t10;
+  const float c12g = 2.f * (m00 * t01 + m10 * t11);
+  const float c22g = m01 * t01 + m11 * t11;
+  // C0 = s [[1 + e^2 - 2 e1, 2 e2], [2 e2, 1 + e^2 + 2 e1]], s = r_e^2 / (1 + e)^2
+  const float re = p.r_e[gidx], e1 = p.e1[gidx], e2 = p.e2[gidx];
+  const float esq = e1 * e1 + e2 * e2, e = sqrtf(esq);
+  const float s = re * re / ((1.f + e) * (1.f + e));
+  const float c11 = s * (1.f + esq - 2.f * e1), c12 = 2.f * s * e2, c22 = s * (1.f + esq + 2.f * e1);
+  const float dlogre = 2.f * (c11g * c11 + c12g * c12 + c22g * c22);
+  float de1 = 0.f, de2 = 0.f;
+  if (e > 0.f) {
+    const float ds1 = -2.f * s / (1.f + e) * (e1 / e), ds2 = -2.f * s / (1.f + e) * (e2 / e);
+    const float a11e = 1.f + esq - 2.f * e1, a22e = 1.f + esq + 2.f * e1;
+    de1 = c11g * (ds1 * a11e + s * (2.f * e1 - 2.f)) + c12g * (ds1 * 2.f * e2) +
+          c22g * (ds1 * a22e + s * (2.f * e1 + 2.f));
+    de2 = c11g * (ds2 * a11e + s * 2.f * e2) + c12g * (ds2 * 2.f * e2 + 2.f * s) +
+          c22g * (ds2 * a22e + s * 2.f * e2);
+  }
+  float* gpo = grad_params + gidx * 6;
+  gpo[0] = dxs;
+  gpo[1] = dys;
+  gpo[2] = dF;
+  gpo[3] = dlogre;
+  gpo[4] = de1;
+  gpo[5] = de2;
+}
+
+}  // namespace gfc

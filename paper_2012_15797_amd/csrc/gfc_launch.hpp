@@ -17,6 +17,11 @@ hipError_t launch_render_small(const RenderArgs& args, hipStream_t stream);
 // Forward render, W = 256 (device scratch allocated stream-ordered per call).
 hipError_t launch_render_w256(const RenderArgs& args, hipStream_t stream);
 
+// Adjoint, W = 256: per-stamp parameter gradients and amplitude partials
+// (device scratch allocated stream-ordered per call).
+hipError_t launch_bwd_w256(const RenderArgs& args, const float* gout, float* grad_params, float* amp_part,
+                           hipStream_t stream);
+
 // PSF spectrum (Section 2, steps 1-2): separable float64 DFT of the S_y x S_x
 // PSF with its centre pixel at frequency-grid index 0.  Writes the
 // lane-permuted main columns, the Nyquist column and optionally the natural

@@ -76,11 +76,11 @@ def assert_close(gpu, ref, what):
                              f"the bound); first {i}: gpu {gpu[i]:.6e} oracle {ref[i]:.6e} bound {bound[i]:.3e}")
 
 
-@pytest.mark.parametrize("W", [16, 32, 64, 128])
+@pytest.mark.parametrize("W", [16, 32, 64, 128, 256])
 def test_backward_each_size(ctx, W):
     rng = np.random.Generator(np.random.PCG64(300 + W))
     cfg = wl.config2(10)
-    n = 40 if W < 128 else 12
+    n = 40 if W < 128 else (12 if W == 128 else 10)
     gal = wl.draw_galaxies(rng, n, W, (np.arange(n) % 2).astype(np.int32), r_e_range=(0.4, W / 5.0))
     g = rng.standard_normal((n, W, W)).astype(np.float32)
     psf, mix = lib_objects(ctx, cfg)
@@ -88,6 +88,24 @@ def test_backward_each_size(ctx, W):
     rp, ra = oracle_grads(cfg, gal, g)
     assert_close(gp, rp, f"params W={W}")
     assert_close(ga, ra, f"amplitudes W={W}")
+    psf.close(); mix.close()
+
+
+def test_backward_w256_across_chunks(ctx):
+    """W = 256 runs in chunks of 1024 stamps over one reused device slab;
+    galaxies on both sides of the chunk boundary, and the last, are checked
+    against the oracle (the others must be finite)."""
+    rng = np.random.Generator(np.random.PCG64(310))
+    cfg = wl.config2(10)
+    W, n = 256, 1030
+    gal = wl.draw_galaxies(rng, n, W, (np.arange(n) % 2).astype(np.int32), r_e_range=(0.4, W / 5.0))
+    g = rng.standard_normal((n, W, W)).astype(np.float32)
+    psf, mix = lib_objects(ctx, cfg)
+    gp, _ = gpu_grads(ctx, psf, mix, gal, W, g)
+    assert np.isfinite(gp).all()
+    idx = [0, 1, 1022, 1023, 1024, 1025, 1029]
+    rp, _ = oracle_grads(cfg, gal.subset(idx), g[idx])
+    assert_close(gp[idx], rp, "params W=256 chunk boundary")
     psf.close(); mix.close()
 
 
