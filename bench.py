@@ -140,8 +140,8 @@ def cpu_baseline(n_total, sample, workers):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--n", type=int, default=100_000)
     ap.add_argument("--cpu-sample", type=int, default=24000)
     ap.add_argument("--cpu-workers", type=int, default=0)

@@ -95,6 +95,29 @@ __device__ __forceinline__ Galaxy load_galaxy(const RenderArgs& p, int64_t g) {
   return G;
 }
 
+__device__ __forceinline__ float uniform_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+
+// For a wavefront (or workgroup) that renders one stamp: the galaxy's values
+// are the same in every lane, so they move to scalar registers.  This frees
+// vector registers and turns the mixture-table reads into scalar loads.
+__device__ __forceinline__ void make_uniform(Galaxy& G) {
+  G.x0 = uniform_f(G.x0);
+  G.y0 = uniform_f(G.y0);
+  G.flux = uniform_f(G.flux);
+  G.fx = uniform_f(G.fx);
+  G.fy = uniform_f(G.fy);
+  G.nx = __builtin_amdgcn_readfirstlane(G.nx);
+  G.ny = __builtin_amdgcn_readfirstlane(G.ny);
+  G.b11 = uniform_f(G.b11);
+  G.b12 = uniform_f(G.b12);
+  G.b22 = uniform_f(G.b22);
+  G.table = __builtin_amdgcn_readfirstlane(G.table);
+  G.K = __builtin_amdgcn_readfirstlane(G.K);
+  G.ok = __builtin_amdgcn_readfirstlane((int)G.ok) != 0;
+}
+
 // Step 4: Fourier weight of a component whose covariance trace is `tr`.
 template <int W>
 __device__ __forceinline__ float route_weight(float tr, unsigned flags) {

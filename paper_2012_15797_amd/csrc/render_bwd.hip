@@ -80,8 +80,7 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
   const int64_t gidx = live ? stamp : p.n - 1;
   Galaxy G = load_galaxy<W>(p, gidx);
   if constexpr (C::SPB == 1) {
-    G.nx = __builtin_amdgcn_readfirstlane(G.nx);
-    G.ny = __builtin_amdgcn_readfirstlane(G.ny);
+    make_uniform(G);
   }
   const float* amp = p.amp + G.table * kKmax;
   const float* var = p.var + G.table * kKmax;

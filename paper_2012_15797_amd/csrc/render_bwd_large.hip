@@ -64,8 +64,7 @@ render_bwd_w256_kernel(RenderArgs p, const float* __restrict__ gout, float* __re
   const int l = threadIdx.x;
   const int64_t gidx = blockIdx.x;  // the launcher sizes each grid to its chunk
   Galaxy G = load_galaxy<W>(p, gidx);
-  G.nx = __builtin_amdgcn_readfirstlane(G.nx);
-  G.ny = __builtin_amdgcn_readfirstlane(G.ny);
+  make_uniform(G);
   const float* amp = p.amp + G.table * kKmax;
   const float* var = p.var + G.table * kKmax;
   const float trB = G.b11 + G.b22;

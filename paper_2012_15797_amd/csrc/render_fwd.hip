@@ -45,6 +45,7 @@ render_small_kernel(RenderArgs p) {
   __shared__ float2 s_t1[C::SPB][C::T1N];
   __shared__ float2 s_py[C::SPB][W + 2];
   __shared__ float2 s_nyq[C::SPB][W];
+  __shared__ float2 s_rs[C::SPB][kKmax];  // (v, (1 - w) A) of the components with a real-space share
 
   const int l = (C::SPB == 1) ? (int)threadIdx.x : (int)threadIdx.x % W;
   const int slot = (C::SPB == 1) ? 0 : (int)threadIdx.x / W;  // keeps the stamp index scalar
@@ -52,8 +53,7 @@ render_small_kernel(RenderArgs p) {
   const bool live = stamp < p.n;
   Galaxy G = load_galaxy<W>(p, live ? stamp : p.n - 1);
   if constexpr (C::SPB == 1) {  // one stamp per wavefront: keep its integer shift in SGPRs
-    G.nx = __builtin_amdgcn_readfirstlane(G.nx);
-    G.ny = __builtin_amdgcn_readfirstlane(G.ny);
+    make_uniform(G);
   }
   const float* amp = p.amp + G.table * kKmax;
   const float* var = p.var + G.table * kKmax;
@@ -98,7 +98,10 @@ render_small_kernel(RenderArgs p) {
     const float v = var[0];
     const float A = amp[0];
     const float w = route_weight<W>(v * trB, p.flags);
-    if (w < 1.f && A != 0.f) rmask = 1u;
+    if (w < 1.f && A != 0.f) {
+      rmask = 1u;
+      if (l == 0) s_rs[slot][0] = make_float2(v, (1.f - w) * A);
+    }
     const float wa = w * A;
     static_for<0, M + 1>([&](auto mm) {
       constexpr int m = decltype(mm)::value;
@@ -113,7 +116,10 @@ render_small_kernel(RenderArgs p) {
     const float v = var[k];
     const float A = (k < G.K) ? amp[k] : 0.f;
     const float w = route_weight<W>(v * trB, p.flags);
-    if (w < 1.f && A != 0.f) rmask |= 1u << k;
+    if (w < 1.f && A != 0.f) {
+      rmask |= 1u << k;
+      if (l == 0) s_rs[slot][k] = make_float2(v, (1.f - w) * A);
+    }
     const float wa = w * A;
     if (wa == 0.f) continue;
     static_for<0, M + 1>([&](auto mm) {
@@ -246,9 +252,8 @@ render_small_kernel(RenderArgs p) {
     const int ybase = (q * C::HR + G.ny) & (W - 1);  // output row of r = 0
     const int rwrap = W - ybase;                      // rows r >= rwrap wrap to the top
     for (unsigned mk = rmask; mk != 0; mk &= mk - 1) {
-      const int k = __builtin_ctz(mk);
-      const float v = var[k];
-      const float ra = (1.f - route_weight<W>(v * trB, p.flags)) * amp[k];
+      const float2 rs = s_rs[slot][__builtin_ctz(mk)];  // LDS, not global: no wait on the stores above
+      const float v = rs.x, ra = rs.y;
       const float sxx = fmaf(v, G.b11, p.pg[2]);
       const float sxy = fmaf(v, G.b12, p.pg[3]);
       const float syy = fmaf(v, G.b22, p.pg[4]);
@@ -270,7 +275,7 @@ render_small_kernel(RenderArgs p) {
       static_for<0, C::HR>([&](auto rr) {
         constexpr int r = decltype(rr)::value;
         float* rowp = outp + ((ybase + r) & (W - 1)) * W;  // uniform when one stamp per wavefront
-        rowp[l] = val[r];
+        __builtin_nontemporal_store(val[r], &rowp[l]);     // streamed: this kernel never reads it back
       });
     }
     __syncthreads();

@@ -44,12 +44,12 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
   __shared__ float2 s_buf[LDS_F2];
   __shared__ float2 s_py[W + 2];
   __shared__ float2 s_nyq[W];
+  __shared__ float2 s_rs[kKmax];  // (v, (1 - w) A) of the components with a real-space share
 
   const int l = threadIdx.x;
   const int64_t stamp = blockIdx.x;  // the launcher sizes the grid to the chunk exactly
   Galaxy G = load_galaxy<W>(p, stamp);
-  G.nx = __builtin_amdgcn_readfirstlane(G.nx);
-  G.ny = __builtin_amdgcn_readfirstlane(G.ny);
+  make_uniform(G);
   const float* amp = p.amp + G.table * kKmax;
   const float* var = p.var + G.table * kKmax;
   const float trB = G.b11 + G.b22;
@@ -90,7 +90,10 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
     const float v = var[k];
     const float A = amp[k];
     const float w = route_weight<W>(v * trB, p.flags);
-    if (w < 1.f && A != 0.f) rmask |= 1u << k;
+    if (w < 1.f && A != 0.f) {
+      rmask |= 1u << k;
+      if (l == 0) s_rs[k] = make_float2(v, (1.f - w) * A);
+    }
     const float wa = w * A;
     if (wa == 0.f) continue;
     static_for<0, M + 1>([&](auto mm) {
@@ -260,9 +263,8 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
     });
     const int srow0 = t * RCH + rh * RPL;
     for (unsigned mk = rmask; mk != 0; mk &= mk - 1) {
-      const int k = __builtin_ctz(mk);
-      const float v = var[k];
-      const float ra = (1.f - route_weight<W>(v * trB, p.flags)) * amp[k];
+      const float2 rs = s_rs[__builtin_ctz(mk)];  // LDS, not global: no wait on the stores above
+      const float v = rs.x, ra = rs.y;
       const float sxx = fmaf(v, G.b11, p.pg[2]);
       const float sxy = fmaf(v, G.b12, p.pg[3]);
       const float syy = fmaf(v, G.b22, p.pg[4]);
@@ -282,7 +284,7 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
     static_for<0, RPL>([&](auto rr) {
       constexpr int r = decltype(rr)::value;
       const int Y = (srow0 + r + G.ny) & (W - 1);
-      outp[Y * W + X] = val[r];
+      __builtin_nontemporal_store(val[r], &outp[Y * W + X]);  // streamed output
     });
     __syncthreads();
   }
