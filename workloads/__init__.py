@@ -20,9 +20,11 @@ from .generate import (  # noqa: F401
     psf_double_gaussian,
     psf_moffat_halo,
     psf_single_gaussian_fit,
+    eigen_psf_moffat,
     draw_galaxies,
     config1,
     config_metric,
+    config_eigen,
     config2,
     config3,
     config4_trace,

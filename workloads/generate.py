@@ -117,6 +117,37 @@ def psf_moffat_halo(S: int = 64, fwhm: float = 4.5, beta: float = 3.0,
     return p / p.sum()
 
 
+def eigen_psf_moffat(S: int = 64, degree: int = 2, image_size: float = 4096.0, n_fit: int = 7):
+    """Synthetic spatially varying PSF in eigen form (components with
+    polynomial amplitudes, as PSF-modelling tools produce them).  The true
+    PSF is a Moffat (beta = 3) whose FWHM and ellipticity drift smoothly
+    over an image_size x image_size field, plus a 1% Gaussian halo.  As such
+    tools do, one component image per polynomial term is fitted by least
+    squares, pixel by pixel, to PSFs sampled on an n_fit x n_fit grid of
+    positions.  Returns dict(comps [T][S][S] float32, coef [T][T] (identity),
+    degree, norm (x_off, x_scale, y_off, y_scale))."""
+    X, Y = _grid(S)
+    half = image_size / 2.0
+    grid = np.linspace(-1.0, 1.0, n_fit)
+    exps = [(a, b) for b in range(degree + 1) for a in range(degree + 1 - b)]
+    rows, imgs = [], []
+    for v in grid:
+        for u in grid:
+            fwhm = 4.5 + 0.4 * u - 0.3 * v + 0.15 * u * v + 0.2 * u * u - 0.1 * v * v
+            q = 1.0 - 0.06 * (u + 0.5 * v)          # axis ratio
+            ang = 0.4 * u - 0.3 * v                  # position angle
+            c, s_ = math.cos(ang), math.sin(ang)
+            Xr, Yr = c * X + s_ * Y, (-s_ * X + c * Y) / q
+            p = 0.99 * _moffat_profile(Xr, Yr, fwhm, 3.0) + 0.01 * _gauss_profile(X, Y, 8.0)
+            imgs.append((p / p.sum()).ravel())
+            rows.append([u**a * v**b for a, b in exps])
+    A = np.array(rows)
+    comps, *_ = np.linalg.lstsq(A, np.array(imgs), rcond=None)
+    T = len(exps)
+    return dict(comps=comps.reshape(T, S, S).astype(np.float32), coef=np.eye(T), degree=degree,
+                norm=np.array([half, half, half, half]))
+
+
 def psf_single_gaussian_fit(P: np.ndarray) -> np.ndarray:
     """Least-squares fit of one centred isotropic Gaussian (variance, amplitude)
     to the PSF pixels.  Returns {mu_x, mu_y, c_xx, c_xy, c_yy, amp} in the
@@ -238,6 +269,20 @@ def config_metric(n=100_000):
     gal = draw_galaxies(rng, n, 64, 0)
     return dict(name="dev8-64x64-moffat", mix=mix, psf=_psf_b().astype(np.float32),
                 psf_gauss=None, gal=gal, flags=0)
+
+
+def config_eigen(n=100_000):
+    """The throughput workload with a spatially varying PSF: n DEV8 galaxies
+    in 64x64 stamps at uniform positions over a 4096 x 4096 image, each
+    rendered with the eigen-PSF evaluated at its position."""
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + 6))
+    dev = dev8_table(rng)
+    mix = mixture_set([dev])
+    gal = draw_galaxies(rng, n, 64, 0)
+    psf_x = rng.uniform(0.0, 4096.0, n).astype(np.float32)
+    psf_y = rng.uniform(0.0, 4096.0, n).astype(np.float32)
+    return dict(name="dev8-64x64-eigenpsf", mix=mix, eig=eigen_psf_moffat(64, 2), gal=gal,
+                psf_x=psf_x, psf_y=psf_y, flags=0)
 
 
 def config2(n=100_000):
