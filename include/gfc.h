@@ -101,7 +101,26 @@ gfc_status gfc_psf_create(gfc_ctx* ctx, const float* pix, int S_y, int S_x,
                           const double* gauss, gfc_psf** out);
 gfc_status gfc_psf_create_f64(gfc_ctx* ctx, const double* pix, int S_y, int S_x,
                               const double* gauss, gfc_psf** out);
-/* Writes the Gaussian approximation in use to gauss_out[6] (host). */
+/* Spatially varying PSF (Section 2, step 2: PSF models whose pixelized
+ * components carry polynomial amplitudes over the image; their transforms
+ * are cached once and weighted per galaxy).  comps: host, J (1..16)
+ * component images [J][S_y][S_x] float32 (copied).  The PSF at image
+ * position (X, Y) is sum_j c_j comps[j] with
+ *   c_j = sum_t coef[j][t] u^a_t v^b_t,  u = (X - norm[0]) / norm[1],
+ *   v = (Y - norm[2]) / norm[3],
+ * over the T = (degree+1)(degree+2)/2 terms with a + b <= degree (0..3),
+ * ordered by the power of v, then of u: 1, u, ..., u^degree, v, u v, ...
+ * coef: host float64 [J][T]; norm: host float64[4] (scales non-zero).
+ * The real-space PSF Gaussian is the moment Gaussian of the PSF at each
+ * galaxy's position (moments about the centre pixel; the summed PSF must
+ * have a positive total there).  Renders with such a PSF need
+ * gfc_galaxies.psf_x/psf_y; the adjoint and the server take constant PSFs
+ * only (GFC_EUNSUPPORTED). */
+gfc_status gfc_psf_create_eigen(gfc_ctx* ctx, const float* comps, int J, int S_y, int S_x,
+                                int degree, const double* coef, const double* norm,
+                                gfc_psf** out);
+/* Writes the Gaussian approximation in use to gauss_out[6] (host).
+ * GFC_EUNSUPPORTED for a spatially varying PSF. */
 gfc_status gfc_psf_gauss(const gfc_psf* psf, double* gauss_out);
 /* Fills the PSF-FT cache for stamp size W on `hip_stream` (the render calls
  * do this lazily on first use of a size).  Cold path: one separable DFT of
@@ -110,6 +129,7 @@ gfc_status gfc_psf_prepare(gfc_psf* psf, int W, void* hip_stream);
 /* Copies the cached PSF spectrum for size W into spec_out (device,
  * [W][W/2+1] interleaved complex float32, natural order: element
  * (k_y, k_x) = sum_{r,c} P[r][c] exp(-2 pi i (k_x (c - S_x/2) + k_y (r - S_y/2)) / W)).
+ * For an eigen-PSF, the J component spectra one after another ([J][W][W/2+1]).
  * Fills the cache first if needed.  Asynchronous on hip_stream. */
 gfc_status gfc_psf_spectrum(gfc_psf* psf, int W, float* spec_out, void* hip_stream);
 /* Synchronises the context's device, then frees the PSF and its caches. */
@@ -145,6 +165,9 @@ typedef struct {
   const float* cd;       /* host, 4 floats {CD11, CD12, CD21, CD22} of the
                             local WCS matrix (pixel -> world), or NULL for the
                             identity; A = CD^{-1} E (Section 2 step 3) */
+  const float* psf_x;    /* device, image position (X, Y) of each galaxy at which */
+  const float* psf_y;    /* a spatially varying PSF is evaluated; required by an
+                            eigen-PSF, ignored (may be NULL) for a constant PSF */
 } gfc_galaxies;
 
 /* Steps 3-8 for n galaxies into stamps of size W, asynchronously on

@@ -37,6 +37,7 @@ class gfc_galaxies(ctypes.Structure):
         ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("flux", ctypes.c_void_p),
         ("r_e", ctypes.c_void_p), ("e1", ctypes.c_void_p), ("e2", ctypes.c_void_p),
         ("mix_id", ctypes.c_void_p), ("cd", ctypes.POINTER(ctypes.c_float)),
+        ("psf_x", ctypes.c_void_p), ("psf_y", ctypes.c_void_p),
     ]
 
 
@@ -65,6 +66,8 @@ PROTOTYPES = {
     "gfc_ctx_invalid_count": (I32, [P, ctypes.POINTER(U64)]),
     "gfc_psf_create": (I32, [P, ctypes.POINTER(ctypes.c_float), I32, I32, ctypes.POINTER(D), PP]),
     "gfc_psf_create_f64": (I32, [P, ctypes.POINTER(D), I32, I32, ctypes.POINTER(D), PP]),
+    "gfc_psf_create_eigen": (I32, [P, ctypes.POINTER(ctypes.c_float), I32, I32, I32, I32, ctypes.POINTER(D),
+                                   ctypes.POINTER(D), PP]),
     "gfc_psf_gauss": (I32, [P, ctypes.POINTER(D)]),
     "gfc_psf_prepare": (I32, [P, I32, P]),
     "gfc_psf_spectrum": (I32, [P, I32, P, P]),

@@ -79,6 +79,31 @@ class Psf:
         self.handle = h
         self.shape = pix.shape
 
+    @classmethod
+    def eigen(cls, ctx: Context, comps, coef, degree: int, norm) -> "Psf":
+        """A spatially varying PSF (gfc_psf_create_eigen): component images
+        [J, S_y, S_x], polynomial coefficients [J, T] over the terms 1, u, ...,
+        v, u v, ... of (u, v) = ((X - norm[0]) / norm[1], (Y - norm[2]) / norm[3])."""
+        self = cls.__new__(cls)
+        self.ctx = ctx
+        c = np.ascontiguousarray(comps, np.float32)
+        if c.ndim != 3:
+            raise ValueError("eigen-PSF components must be [J, S_y, S_x]")
+        T = (degree + 1) * (degree + 2) // 2
+        cf = np.ascontiguousarray(coef, np.float64)
+        if cf.shape != (c.shape[0], T):
+            raise ValueError(f"coef must be [J, {T}] for degree {degree}")
+        nm = np.ascontiguousarray(norm, np.float64).reshape(4)
+        h = ctypes.c_void_p()
+        call("gfc_psf_create_eigen", ctx.handle, c.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+             c.shape[0], c.shape[1], c.shape[2], int(degree),
+             cf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+             nm.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(h))
+        self.handle = h
+        self.shape = c.shape[1:]
+        self.n_components = c.shape[0]
+        return self
+
     @property
     def gauss(self) -> np.ndarray:
         out = (ctypes.c_double * 6)()
@@ -89,11 +114,14 @@ class Psf:
         call("gfc_psf_prepare", self.handle, int(W), _stream_ptr(self.ctx.device))
 
     def spectrum(self, W: int) -> torch.Tensor:
-        """The cached PSF spectrum for stamp size W, complex64 [W, W/2+1]."""
-        out = torch.empty((W, W // 2 + 1, 2), dtype=torch.float32, device=self.ctx.torch_device)
+        """The cached PSF spectrum for stamp size W, complex64 [W, W/2+1]
+        ([J, W, W/2+1] for an eigen-PSF)."""
+        J = getattr(self, "n_components", 0)
+        out = torch.empty((max(J, 1), W, W // 2 + 1, 2), dtype=torch.float32, device=self.ctx.torch_device)
         call("gfc_psf_spectrum", self.handle, int(W), ctypes.c_void_p(out.data_ptr()),
              _stream_ptr(self.ctx.device))
-        return torch.view_as_complex(out)
+        out = torch.view_as_complex(out)
+        return out if J else out[0]
 
     def close(self):
         if self.handle:
@@ -139,7 +167,7 @@ class Mixture:
             self.handle = None
 
 
-def _galaxies(dev, x, y, flux, r_e, e1, e2, mix_id, cd):
+def _galaxies(dev, x, y, flux, r_e, e1, e2, mix_id, cd, psf_x=None, psf_y=None):
     ts = [_f32_dev(t, dev, nm) for t, nm in
           zip((x, y, flux, r_e, e1, e2), ("x", "y", "flux", "r_e", "e1", "e2"))]
     n = ts[0].numel()
@@ -158,16 +186,25 @@ def _galaxies(dev, x, y, flux, r_e, e1, e2, mix_id, cd):
     if cd is not None:
         cdbuf = (ctypes.c_float * 4)(*[float(v) for v in np.asarray(cd).reshape(4)])
         g.cd = ctypes.cast(cdbuf, ctypes.POINTER(ctypes.c_float))
-    keep = (ts, mid, cdbuf)
+    pos = None
+    if psf_x is not None or psf_y is not None:
+        if psf_x is None or psf_y is None:
+            raise ValueError("psf_x and psf_y go together")
+        pos = (_f32_dev(psf_x, dev, "psf_x"), _f32_dev(psf_y, dev, "psf_y"))
+        if pos[0].numel() != n or pos[1].numel() != n:
+            raise ValueError("psf_x/psf_y length differs")
+        g.psf_x, g.psf_y = pos[0].data_ptr(), pos[1].data_ptr()
+    keep = (ts, mid, cdbuf, pos)
     return g, n, keep
 
 
 def gfc_render_stamps(ctx, psf, mix, x, y, flux, r_e, e1, e2, W, mix_id=None, flags=0, cd=None,
-                      out=None):
+                      out=None, psf_x=None, psf_y=None):
     """Forward render (gfc_render_stamps): float32 stamps [n, W, W] on the
-    context's device, enqueued on torch's current stream."""
+    context's device, enqueued on torch's current stream.  psf_x/psf_y: the
+    galaxies' image positions, for a spatially varying PSF."""
     dev = ctx.torch_device
-    g, n, keep = _galaxies(dev, x, y, flux, r_e, e1, e2, mix_id, cd)
+    g, n, keep = _galaxies(dev, x, y, flux, r_e, e1, e2, mix_id, cd, psf_x, psf_y)
     if out is None:
         out = torch.empty((n, W, W), dtype=torch.float32, device=dev)
     elif out.dtype != torch.float32 or not out.is_contiguous() or out.numel() != n * W * W:

@@ -39,7 +39,19 @@ struct RenderArgs {
   int64_t n;
   unsigned flags;
   unsigned long long* invalid;  // device counter of invalid galaxies
+  // Spatially varying (eigen-)PSF; eig_J == 0 for a constant PSF.
+  int eig_J;                // components; their spectra follow each other eig_stride float2 apart
+  int eig_degree;           // polynomial degree (0..3)
+  int64_t eig_stride;
+  const float* eig_coef;    // [J][T], T = (degree + 1)(degree + 2) / 2
+  const float* eig_mom;     // [J][6]: sum, sum x, sum y, sum x^2, sum x y, sum y^2 about the centre pixel
+  float eig_norm[4];        // x_off, 1 / x_scale, y_off, 1 / y_scale
+  const float* psf_px;      // [n] image position of each galaxy (eigen PSF only)
+  const float* psf_py;
 };
+
+constexpr int kEigMax = 16;     // eigen-PSF components
+constexpr int kEigDegMax = 3;   // polynomial degree
 
 enum : unsigned { kForceFourier = 1u, kForceReal = 2u, kRampLinear = 4u };
 
@@ -116,6 +128,37 @@ __device__ __forceinline__ void make_uniform(Galaxy& G) {
   G.table = __builtin_amdgcn_readfirstlane(G.table);
   G.K = __builtin_amdgcn_readfirstlane(G.K);
   G.ok = __builtin_amdgcn_readfirstlane((int)G.ok) != 0;
+}
+
+// Weight of eigen-PSF component j at normalised position (u, v): the sum
+// over polynomial terms u^a v^b (a + b <= degree, ordered by the power of v,
+// then of u) of the component's coefficients.  up/vp hold powers 0..3.
+__device__ __forceinline__ float eigen_weight(const RenderArgs& p, int j, const float (&up)[kEigDegMax + 1],
+                                              const float (&vp)[kEigDegMax + 1]) {
+  const int D = p.eig_degree;
+  const float* cf = p.eig_coef + j * ((D + 1) * (D + 2) / 2);
+  float c = 0.f;
+  static_for<0, kEigDegMax + 1>([&](auto bb) {
+    constexpr int b = decltype(bb)::value;
+    static_for<0, kEigDegMax + 1 - b>([&](auto aa) {
+      constexpr int a = decltype(aa)::value;
+      if (a + b <= D) c = fmaf(cf[b * (D + 1) - b * (b - 1) / 2 + a], up[a] * vp[b], c);
+    });
+  });
+  return c;
+}
+
+// The PSF Gaussian {mu_x, mu_y, c_xx, c_xy, c_yy, amp} of the weighted sum
+// of components: moments are linear in the weights.
+__device__ __forceinline__ void eigen_gauss(const float (&mom)[6], float (&pg)[6]) {
+  const float F = mom[0], rF = 1.f / F;
+  const float mx = mom[1] * rF, my = mom[2] * rF;
+  pg[0] = mx;
+  pg[1] = my;
+  pg[2] = fmaf(mom[3], rF, -mx * mx);
+  pg[3] = fmaf(mom[4], rF, -mx * my);
+  pg[4] = fmaf(mom[5], rF, -my * my);
+  pg[5] = F;
 }
 
 // Step 4: Fourier weight of a component whose covariance trace is `tr`.

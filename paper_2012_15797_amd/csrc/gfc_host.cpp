@@ -52,7 +52,9 @@ gfc_status psf_cache(gfc_psf* psf, int W, hipStream_t stream, const PsfSpectrum*
   }
   PsfSpectrum spec;
   const size_t main_n = (size_t)(W / 2) * W, nyq_n = (size_t)W;
-  hipError_t e = hipMalloc(&spec.main_cols, (main_n + nyq_n) * sizeof(float2));
+  const int ncomp = psf->J > 0 ? psf->J : 1;
+  spec.stride = (int64_t)(main_n + nyq_n);
+  hipError_t e = hipMalloc(&spec.main_cols, (size_t)ncomp * (main_n + nyq_n) * sizeof(float2));
   if (e != hipSuccess) return fail(GFC_ENOMEM, "PSF cache allocation failed");
   spec.nyq_col = spec.main_cols + main_n;
   double2* tmp = nullptr;
@@ -61,8 +63,12 @@ gfc_status psf_cache(gfc_psf* psf, int W, hipStream_t stream, const PsfSpectrum*
     hipFree(spec.main_cols);
     return fail(GFC_ENOMEM, "PSF cache scratch allocation failed");
   }
-  e = launch_psf_spectrum(psf->d_pix, psf->Sy, psf->Sx, W, tmp, spec.main_cols, spec.nyq_col,
-                          nullptr, stream);
+  // One transform per component (one for a constant PSF); the same stream
+  // orders the reuse of tmp.
+  for (int j = 0; j < ncomp && e == hipSuccess; ++j)
+    e = launch_psf_spectrum(psf->d_pix + (size_t)j * psf->Sy * psf->Sx, psf->Sy, psf->Sx, W, tmp,
+                            spec.main_cols + j * spec.stride, spec.nyq_col + j * spec.stride, nullptr,
+                            stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   hipFree(tmp);
   if (e != hipSuccess) {
@@ -112,10 +118,31 @@ gfc_status fill_render_args(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix* mix, cons
     a->cdinv[3] = 1.f;
   }
   for (int i = 0; i < 6; ++i) a->pg[i] = (float)psf->gauss[i];
+  if (psf->J > 0) {
+    if (n > 0 && (!gal->psf_x || !gal->psf_y))
+      return fail(GFC_EINVAL, "a spatially varying PSF needs psf_x and psf_y for every galaxy");
+    const int T = (psf->degree + 1) * (psf->degree + 2) / 2;
+    a->eig_J = psf->J;
+    a->eig_degree = psf->degree;
+    a->eig_coef = psf->d_eig;
+    a->eig_mom = psf->d_eig + (size_t)psf->J * T;
+    a->eig_norm[0] = (float)psf->norm[0];
+    a->eig_norm[1] = (float)(1.0 / psf->norm[1]);
+    a->eig_norm[2] = (float)psf->norm[2];
+    a->eig_norm[3] = (float)(1.0 / psf->norm[3]);
+    a->psf_px = gal->psf_x;
+    a->psf_py = gal->psf_y;
+  }
   a->n = n;
   a->flags = flags;
   a->invalid = ctx->d_invalid;
   return GFC_OK;
+}
+
+void attach_spectrum(RenderArgs* a, const PsfSpectrum* spec) {
+  a->psf_main = spec->main_cols;
+  a->psf_nyq = spec->nyq_col;
+  a->eig_stride = spec->stride;
 }
 
 }  // namespace gfc
@@ -290,8 +317,71 @@ gfc_status gfc_psf_create(gfc_ctx* ctx, const float* pix, int Sy, int Sx, const 
   return psf_create_impl(ctx, d.data(), Sy, Sx, gauss, out);
 }
 
+gfc_status gfc_psf_create_eigen(gfc_ctx* ctx, const float* comps, int J, int Sy, int Sx, int degree,
+                                const double* coef, const double* norm, gfc_psf** out) {
+  if (!ctx || !comps || !coef || !norm || !out) return fail(GFC_EINVAL, "null argument");
+  *out = nullptr;
+  if (J < 1 || J > kEigMax) return fail(GFC_EINVAL, "eigen-PSF needs 1..16 components");
+  if (degree < 0 || degree > kEigDegMax) return fail(GFC_EINVAL, "eigen-PSF polynomial degree must be 0..3");
+  if (Sy < 2 || Sx < 2 || Sy > 1024 || Sx > 1024 || (Sy & 1) || (Sx & 1))
+    return fail(GFC_EINVAL, "PSF sides must be even, 2..1024");
+  if (!(std::isfinite(norm[0]) && std::isfinite(norm[2]) && std::isfinite(norm[1]) && std::isfinite(norm[3]) &&
+        norm[1] != 0.0 && norm[3] != 0.0))
+    return fail(GFC_EINVAL, "eigen-PSF normalisation must be finite with non-zero scales");
+  const int T = (degree + 1) * (degree + 2) / 2;
+  const size_t npix = (size_t)Sy * Sx;
+  std::vector<double> pix((size_t)J * npix);
+  // device block: coefficients [J][T] then raw moments about the centre pixel [J][6]
+  std::vector<float> eig((size_t)J * T + (size_t)J * 6);
+  for (int j = 0; j < J; ++j) {
+    for (int t = 0; t < T; ++t) {
+      const double c = coef[(size_t)j * T + t];
+      if (!std::isfinite(c)) return fail(GFC_EINVAL, "non-finite eigen-PSF coefficient");
+      eig[(size_t)j * T + t] = (float)c;
+    }
+    double m[6] = {0, 0, 0, 0, 0, 0};
+    for (int r = 0; r < Sy; ++r)
+      for (int c = 0; c < Sx; ++c) {
+        const double v = comps[(size_t)j * npix + (size_t)r * Sx + c];
+        if (!std::isfinite(v)) return fail(GFC_EINVAL, "non-finite eigen-PSF pixel");
+        pix[(size_t)j * npix + (size_t)r * Sx + c] = v;
+        const double x = c - Sx / 2, y = r - Sy / 2;
+        m[0] += v;
+        m[1] += v * x;
+        m[2] += v * y;
+        m[3] += v * x * x;
+        m[4] += v * x * y;
+        m[5] += v * y * y;
+      }
+    for (int i = 0; i < 6; ++i) eig[(size_t)J * T + (size_t)j * 6 + i] = (float)m[i];
+  }
+  DeviceGuard guard(ctx->device);
+  auto* psf = new (std::nothrow) gfc_psf();
+  if (!psf) return fail(GFC_ENOMEM, "PSF allocation failed");
+  psf->ctx = ctx;
+  psf->Sy = Sy;
+  psf->Sx = Sx;
+  psf->J = J;
+  psf->degree = degree;
+  std::memcpy(psf->norm, norm, sizeof(psf->norm));
+  hipError_t e = hipMalloc(&psf->d_pix, pix.size() * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&psf->d_eig, eig.size() * sizeof(float));
+  if (e == hipSuccess) e = hipMemcpy(psf->d_pix, pix.data(), pix.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(psf->d_eig, eig.data(), eig.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    hipFree(psf->d_pix);
+    hipFree(psf->d_eig);
+    delete psf;
+    return hip_fail(e, "eigen-PSF upload");
+  }
+  ctx->n_objects++;
+  *out = psf;
+  return GFC_OK;
+}
+
 gfc_status gfc_psf_gauss(const gfc_psf* psf, double* gauss_out) {
   if (!psf || !gauss_out) return fail(GFC_EINVAL, "null argument");
+  if (psf->J > 0) return fail(GFC_EUNSUPPORTED, "the Gaussian of a spatially varying PSF depends on position");
   std::memcpy(gauss_out, psf->gauss, sizeof(psf->gauss));
   return GFC_OK;
 }
@@ -322,8 +412,11 @@ gfc_status gfc_psf_spectrum(gfc_psf* psf, int W, float* spec_out, void* hip_stre
     hipFree(tmp);
     return fail(GFC_ENOMEM, "scratch allocation failed");
   }
-  e = launch_psf_spectrum(psf->d_pix, psf->Sy, psf->Sx, W, tmp, m, m + (size_t)(W / 2) * W,
-                          reinterpret_cast<float2*>(spec_out), s);
+  const int ncomp = psf->J > 0 ? psf->J : 1;
+  for (int j = 0; j < ncomp && e == hipSuccess; ++j)
+    e = launch_psf_spectrum(psf->d_pix + (size_t)j * psf->Sy * psf->Sx, psf->Sy, psf->Sx, W, tmp, m,
+                            m + (size_t)(W / 2) * W,
+                            reinterpret_cast<float2*>(spec_out) + (size_t)j * W * (W / 2 + 1), s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   hipFree(tmp);
   hipFree(m);
@@ -337,6 +430,7 @@ gfc_status gfc_psf_destroy(gfc_psf* psf) {
   hipDeviceSynchronize();
   for (auto& kv : psf->cache) hipFree(kv.second.main_cols);
   hipFree(psf->d_pix);
+  hipFree(psf->d_eig);
   psf->ctx->n_objects--;
   delete psf;
   return GFC_OK;
@@ -425,8 +519,7 @@ gfc_status gfc_render_stamps(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix* mix, con
   const PsfSpectrum* spec = nullptr;
   st = psf_cache(psf, W, s, &spec);
   if (st != GFC_OK) return st;
-  a.psf_main = spec->main_cols;
-  a.psf_nyq = spec->nyq_col;
+  attach_spectrum(&a, spec);
   a.out = out;
   return render_launch(a, W, s);
 }

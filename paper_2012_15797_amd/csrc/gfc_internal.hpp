@@ -24,14 +24,20 @@ struct PsfSpectrum {
   int W = 0;
   float2* main_cols = nullptr;  // [W/2][W] (one allocation with nyq_col)
   float2* nyq_col = nullptr;    // [W]
+  int64_t stride = 0;           // float2 from one eigen-PSF component's spectrum to the next
 };
 }  // namespace gfc
 
 struct gfc_psf {
   gfc_ctx* ctx = nullptr;
   int Sy = 0, Sx = 0;
-  double* d_pix = nullptr;  // device, float64 [Sy][Sx]
+  double* d_pix = nullptr;  // device, float64 [J or 1][Sy][Sx]
   double gauss[6] = {0, 0, 0, 0, 0, 0};
+  // Spatially varying (eigen-)PSF: J > 0 components with polynomial weights.
+  int J = 0;
+  int degree = 0;
+  double norm[4] = {0, 1, 0, 1};  // x_off, x_scale, y_off, y_scale
+  float* d_eig = nullptr;         // device: coefficients [J][T], then raw moments [J][6]
   std::mutex mu;
   std::map<int, gfc::PsfSpectrum> cache;
 };
@@ -65,6 +71,8 @@ class DeviceGuard {
 gfc_status psf_cache(gfc_psf* psf, int W, hipStream_t stream, const PsfSpectrum** out);
 gfc_status fill_render_args(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix* mix, const gfc_galaxies* gal,
                             int64_t n, int W, unsigned flags, RenderArgs* a);
+// Points the render arguments at a cached spectrum.
+void attach_spectrum(RenderArgs* a, const PsfSpectrum* spec);
 // Launches the forward kernels for stamp size W (arguments already validated).
 gfc_status render_launch(const RenderArgs& a, int W, hipStream_t stream);
 

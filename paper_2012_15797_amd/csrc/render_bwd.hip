@@ -425,6 +425,7 @@ gfc_status gfc_render_stamps_backward(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix*
                                       int64_t n, int W, unsigned flags, const float* grad_out,
                                       float* grad_params, float* grad_amp, void* workspace,
                                       void* hip_stream) {
+  if (psf && psf->J > 0) return fail(GFC_EUNSUPPORTED, "the adjoint takes a constant PSF");
   RenderArgs a;
   gfc_status st = fill_render_args(ctx, psf, mix, gal, n, W, flags, &a);
   if (st != GFC_OK) return st;
@@ -435,8 +436,7 @@ gfc_status gfc_render_stamps_backward(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix*
   const PsfSpectrum* spec = nullptr;
   st = psf_cache(psf, W, s, &spec);
   if (st != GFC_OK) return st;
-  a.psf_main = spec->main_cols;
-  a.psf_nyq = spec->nyq_col;
+  attach_spectrum(&a, spec);
   float* ws = static_cast<float*>(workspace);
   bool own = false;
   hipError_t e = hipSuccess;

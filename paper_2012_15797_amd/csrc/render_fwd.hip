@@ -36,7 +36,10 @@ struct SmallCfg {
   static constexpr int HR = W / 2;               // rows of the store tile per pass
 };
 
-template <int W>
+// EIG: the PSF varies over the image (eigen-PSF components with polynomial
+// weights); its spectrum and Gaussian are formed per stamp from the
+// components' cached spectra and moments.
+template <int W, bool EIG>
 __global__ void __launch_bounds__(SmallCfg<W>::BLOCK)
 render_small_kernel(RenderArgs p) {
   using C = SmallCfg<W>;
@@ -132,6 +135,49 @@ render_small_kernel(RenderArgs p) {
     });
   }
 
+  // PSF spectrum of this lane's bins and the PSF Gaussian (step 2; for a
+  // varying PSF, the weighted sum of the components at the galaxy's image
+  // position, whose transforms and moments are linear in the weights).
+  float2 Pm[M];
+  float2 psfN;
+  float pg[6];
+  if constexpr (EIG) {
+    const int64_t g = live ? stamp : p.n - 1;
+    float u = (p.psf_px[g] - p.eig_norm[0]) * p.eig_norm[1];
+    float v = (p.psf_py[g] - p.eig_norm[2]) * p.eig_norm[3];
+    if constexpr (C::SPB == 1) {
+      u = uniform_f(u);
+      v = uniform_f(v);
+    }
+    const float up[4] = {1.f, u, u * u, u * u * u}, vp[4] = {1.f, v, v * v, v * v * v};
+    static_for<0, M>([&](auto mm) { Pm[decltype(mm)::value] = make_float2(0.f, 0.f); });
+    psfN = make_float2(0.f, 0.f);
+    float mom[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < p.eig_J; ++j) {
+      const float cj = eigen_weight(p, j, up, vp);
+      const float2* pj = p.psf_main + j * p.eig_stride;
+      static_for<0, M>([&](auto mm) {
+        constexpr int m = decltype(mm)::value;
+        const float2 q = pj[m * W + l];
+        Pm[m] = make_float2(fmaf(cj, q.x, Pm[m].x), fmaf(cj, q.y, Pm[m].y));
+      });
+      const float2 qn = p.psf_nyq[j * p.eig_stride + l];
+      psfN = make_float2(fmaf(cj, qn.x, psfN.x), fmaf(cj, qn.y, psfN.y));
+      static_for<0, 6>([&](auto ii) {
+        constexpr int i = decltype(ii)::value;
+        mom[i] = fmaf(cj, p.eig_mom[j * 6 + i], mom[i]);
+      });
+    }
+    eigen_gauss(mom, pg);
+  } else {
+    static_for<0, M>([&](auto mm) {
+      constexpr int m = decltype(mm)::value;
+      Pm[m] = p.psf_main[m * W + l];
+    });
+    psfN = p.psf_nyq[l];
+    static_for<0, 6>([&](auto ii) { pg[decltype(ii)::value] = p.pg[decltype(ii)::value]; });
+  }
+
   // Fractional-shift phases (shift theorem): exp(-2 pi i (fx nu + fy om)).
   float sx, cx;
   sincospif(-2.f * G.fx * nu, &sx, &cx);
@@ -153,14 +199,14 @@ render_small_kernel(RenderArgs p) {
     const float2 plus = cadd(cscale(pyA, SN[0]), cscale(pyB, SN[2]));
     const float2 minus = cadd(cscale(pyA, SN[1]), cscale(pyB, SN[3]));
     const float2 inner = cadd(cmul(eM, plus), cmul(eP, minus));
-    s_nyq[slot][l] = cmul(cscale(p.psf_nyq[l], 0.5f * fs), inner);
+    s_nyq[slot][l] = cmul(cscale(psfN, 0.5f * fs), inner);
   }
   __syncthreads();
 
   float2 Z[M];
   static_for<0, M>([&](auto mm) {
     constexpr int m = decltype(mm)::value;
-    const float2 P = p.psf_main[m * W + l];
+    const float2 P = Pm[m];
     if constexpr (2 * m == W / 2) {
       const float2 q0 = s_py[slot][W / 2 + h];
       const float2 pyA = h ? q0 : cscale(q0, 0.5f);
@@ -230,8 +276,8 @@ render_small_kernel(RenderArgs p) {
   // q stages source rows q W/2 .. q W/2 + W/2 - 1 in LDS; they land on output
   // rows (q W/2 + r + ny) mod W.
   float* st = reinterpret_cast<float*>(&s_t1[slot][0]);
-  const float dx = (float)l - G.x0 - p.pg[0];
-  const float dyc = -G.y0 - p.pg[1];
+  const float dx = (float)l - G.x0 - pg[0];
+  const float dyc = -G.y0 - pg[1];
   float* outp = p.out + (live ? stamp : 0) * (int64_t)(W * W);
   const int colsrc = (l - G.nx) & (W - 1);
   static_for<0, 2>([&](auto qq) {
@@ -254,12 +300,12 @@ render_small_kernel(RenderArgs p) {
     for (unsigned mk = rmask; mk != 0; mk &= mk - 1) {
       const float2 rs = s_rs[slot][__builtin_ctz(mk)];  // LDS, not global: no wait on the stores above
       const float v = rs.x, ra = rs.y;
-      const float sxx = fmaf(v, G.b11, p.pg[2]);
-      const float sxy = fmaf(v, G.b12, p.pg[3]);
-      const float syy = fmaf(v, G.b22, p.pg[4]);
+      const float sxx = fmaf(v, G.b11, pg[2]);
+      const float sxy = fmaf(v, G.b12, pg[3]);
+      const float syy = fmaf(v, G.b22, pg[4]);
       const float det = fmaf(sxx, syy, -(sxy * sxy));
       const float rdet = __builtin_amdgcn_rcpf(det);
-      const float ampr = ra * G.flux * p.pg[5] * kInv2Pi * __builtin_amdgcn_rsqf(det);
+      const float ampr = ra * G.flux * pg[5] * kInv2Pi * __builtin_amdgcn_rsqf(det);
       const float a0 = kHalfLog2e * (syy * rdet) * dx * dx;
       const float a1 = -2.f * kHalfLog2e * (sxy * rdet) * dx;
       const float a2 = kHalfLog2e * (sxx * rdet);
@@ -299,9 +345,14 @@ hipError_t launch_render_small(const RenderArgs& args, hipStream_t stream) {
     p.e2 = args.e2 + done;
     p.mix_id = args.mix_id ? args.mix_id + done : nullptr;
     p.out = args.out + done * (int64_t)W * W;
+    p.psf_px = args.psf_px ? args.psf_px + done : nullptr;
+    p.psf_py = args.psf_py ? args.psf_py + done : nullptr;
     p.n = chunk;
     const unsigned blocks = (unsigned)((chunk + C::SPB - 1) / C::SPB);
-    hipLaunchKernelGGL(render_small_kernel<W>, dim3(blocks), dim3(C::BLOCK), 0, stream, p);
+    if (args.eig_J > 0)
+      hipLaunchKernelGGL((render_small_kernel<W, true>), dim3(blocks), dim3(C::BLOCK), 0, stream, p);
+    else
+      hipLaunchKernelGGL((render_small_kernel<W, false>), dim3(blocks), dim3(C::BLOCK), 0, stream, p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     done += chunk;

@@ -38,6 +38,8 @@ constexpr int LDS_F2 = CCH * D * M;
 static_assert(LDS_F2 == 2 * RCH * (W / 4), "shared buffer sizes differ");
 }  // namespace big
 
+// EIG: spatially varying PSF (eigen-PSF components with polynomial weights).
+template <bool EIG>
 __global__ void __launch_bounds__(big::BLOCK)
 render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
   using namespace big;
@@ -45,6 +47,7 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
   __shared__ float2 s_py[W + 2];
   __shared__ float2 s_nyq[W];
   __shared__ float2 s_rs[kKmax];  // (v, (1 - w) A) of the components with a real-space share
+  __shared__ float s_cj[kEigMax];  // eigen-PSF component weights at this galaxy's position
 
   const int l = threadIdx.x;
   const int64_t stamp = blockIdx.x;  // the launcher sizes the grid to the chunk exactly
@@ -108,6 +111,34 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
     }
   }
 
+  // PSF Gaussian and Nyquist-column PSF value (step 2; for a varying PSF the
+  // weighted sums of the components' moments and transforms).
+  float pg[6];
+  float2 psfN = make_float2(0.f, 0.f);
+  if constexpr (EIG) {
+    const float u = uniform_f((p.psf_px[stamp] - p.eig_norm[0]) * p.eig_norm[1]);
+    const float v = uniform_f((p.psf_py[stamp] - p.eig_norm[2]) * p.eig_norm[3]);
+    const float up[4] = {1.f, u, u * u, u * u * u}, vp[4] = {1.f, v, v * v, v * v * v};
+    if (l < p.eig_J) s_cj[l] = eigen_weight(p, l, up, vp);
+    __syncthreads();
+    float mom[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < p.eig_J; ++j) {
+      const float cj = s_cj[j];
+      static_for<0, 6>([&](auto ii) {
+        constexpr int i = decltype(ii)::value;
+        mom[i] = fmaf(cj, p.eig_mom[j * 6 + i], mom[i]);
+      });
+      if (nyq_lane) {
+        const float2 qn = p.psf_nyq[j * p.eig_stride + l];
+        psfN = make_float2(fmaf(cj, qn.x, psfN.x), fmaf(cj, qn.y, psfN.y));
+      }
+    }
+    eigen_gauss(mom, pg);
+  } else {
+    static_for<0, 6>([&](auto ii) { pg[decltype(ii)::value] = p.pg[decltype(ii)::value]; });
+    if (nyq_lane) psfN = p.psf_nyq[l];
+  }
+
   float sx, cx;
   sincospif(-2.f * G.fx * nu, &sx, &cx);
   const float fs = G.flux * (1.f / ((float)W * (float)W));
@@ -125,14 +156,24 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
     const float2 pyB = corner ? make_float2(0.5f * cym, 0.5f * sym) : make_float2(0.f, 0.f);
     const float2 plus = cadd(cscale(pyA, SN[0]), cscale(pyB, SN[2]));
     const float2 minus = cadd(cscale(pyA, SN[1]), cscale(pyB, SN[3]));
-    s_nyq[l] = cmul(cscale(p.psf_nyq[l], 0.5f * fs), cadd(cmul(eM, plus), cmul(eP, minus)));
+    s_nyq[l] = cmul(cscale(psfN, 0.5f * fs), cadd(cmul(eM, plus), cmul(eP, minus)));
   }
   __syncthreads();
 
   float2 Z[M];
   static_for<0, M>([&](auto mm) {
     constexpr int m = decltype(mm)::value;
-    const float2 P = p.psf_main[m * BLOCK + l];
+    float2 P;
+    if constexpr (EIG) {
+      P = make_float2(0.f, 0.f);
+      for (int j = 0; j < p.eig_J; ++j) {
+        const float cj = s_cj[j];
+        const float2 q = p.psf_main[j * p.eig_stride + m * BLOCK + l];
+        P = make_float2(fmaf(cj, q.x, P.x), fmaf(cj, q.y, P.y));
+      }
+    } else {
+      P = p.psf_main[m * BLOCK + l];
+    }
     if constexpr (D * m == W / 2) {
       const float2 q0 = s_py[W / 2 + h];
       const float2 pyA = h ? q0 : cscale(q0, 0.5f);
@@ -239,7 +280,7 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
   const bool odd = xs & 1;
   const float ca = sg * (odd ? tw.y : tw.x);
   const float cb = sg * (odd ? tw.x : -tw.y);
-  const float dx = (float)X - G.x0 - p.pg[0];
+  const float dx = (float)X - G.x0 - pg[0];
   float* outp = p.out + stamp * (int64_t)(W * W);
   for (int t = 0; t < W / RCH; ++t) {
     if ((wv >> 1) == t) {
@@ -265,19 +306,19 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
     for (unsigned mk = rmask; mk != 0; mk &= mk - 1) {
       const float2 rs = s_rs[__builtin_ctz(mk)];  // LDS, not global: no wait on the stores above
       const float v = rs.x, ra = rs.y;
-      const float sxx = fmaf(v, G.b11, p.pg[2]);
-      const float sxy = fmaf(v, G.b12, p.pg[3]);
-      const float syy = fmaf(v, G.b22, p.pg[4]);
+      const float sxx = fmaf(v, G.b11, pg[2]);
+      const float sxy = fmaf(v, G.b12, pg[3]);
+      const float syy = fmaf(v, G.b22, pg[4]);
       const float det = fmaf(sxx, syy, -(sxy * sxy));
       const float rdet = __builtin_amdgcn_rcpf(det);
-      const float ampr = ra * G.flux * p.pg[5] * kInv2Pi * __builtin_amdgcn_rsqf(det);
+      const float ampr = ra * G.flux * pg[5] * kInv2Pi * __builtin_amdgcn_rsqf(det);
       const float a0 = kHalfLog2e * (syy * rdet) * dx * dx;
       const float a1 = -2.f * kHalfLog2e * (sxy * rdet) * dx;
       const float a2 = kHalfLog2e * (sxx * rdet);
       static_for<0, RPL>([&](auto rr) {
         constexpr int r = decltype(rr)::value;
         const int Y = (srow0 + r + G.ny) & (W - 1);
-        const float dy = (float)Y - G.y0 - p.pg[1];
+        const float dy = (float)Y - G.y0 - pg[1];
         val[r] = fmaf(ampr, __builtin_amdgcn_exp2f(fmaf(dy, fmaf(a2, dy, a1), a0)), val[r]);
       });
     }
@@ -309,8 +350,13 @@ hipError_t launch_render_w256(const RenderArgs& args, hipStream_t stream) {
     p.e2 = args.e2 + done;
     p.mix_id = args.mix_id ? args.mix_id + done : nullptr;
     p.out = args.out + done * (int64_t)W * W;
+    p.psf_px = args.psf_px ? args.psf_px + done : nullptr;
+    p.psf_py = args.psf_py ? args.psf_py + done : nullptr;
     p.n = chunk;
-    hipLaunchKernelGGL(render_w256_kernel, dim3((unsigned)chunk), dim3(BLOCK), 0, stream, p, scratch);
+    if (args.eig_J > 0)
+      hipLaunchKernelGGL(render_w256_kernel<true>, dim3((unsigned)chunk), dim3(BLOCK), 0, stream, p, scratch);
+    else
+      hipLaunchKernelGGL(render_w256_kernel<false>, dim3((unsigned)chunk), dim3(BLOCK), 0, stream, p, scratch);
     e = hipGetLastError();
     if (e != hipSuccess) break;
   }

@@ -325,7 +325,7 @@ class HipExecutor : public Executor {
     if (hipMemcpyAsync(dpar, hp, par_bytes, hipMemcpyHostToDevice, s) != hipSuccess) return fail_batch(b);
     const PsfSpectrum* spec = nullptr;
     if (psf_cache(r0->psf, W, s, &spec) != GFC_OK) return fail_batch(b);
-    gfc_galaxies gal;
+    gfc_galaxies gal{};
     gal.x = dpar;
     gal.y = dpar + n;
     gal.flux = dpar + 2 * n;
@@ -336,8 +336,7 @@ class HipExecutor : public Executor {
     gal.cd = nullptr;
     RenderArgs a;
     if (fill_render_args(ctx_, r0->psf, r0->mix, &gal, n, W, r0->flags, &a) != GFC_OK) return fail_batch(b);
-    a.psf_main = spec->main_cols;
-    a.psf_nyq = spec->nyq_col;
+    attach_spectrum(&a, spec);
     a.out = dout;
     if (render_launch(a, W, s) != GFC_OK) return fail_batch(b);
     b.event = events_[b.stream];
@@ -454,6 +453,7 @@ gfc_status gfc_server_submit(gfc_server* s, const gfc_request* q, uint64_t* tick
   if (!q->psf || !q->mix || q->psf->ctx != s->ctx || q->mix->ctx != s->ctx)
     return fail(GFC_EINVAL, "request PSF or mixture missing or from another context");
   if (!stamp_size_ok(q->W)) return fail(GFC_EINVAL, "unsupported stamp size");
+  if (q->psf->J > 0) return fail(GFC_EUNSUPPORTED, "requests take constant PSFs (no per-galaxy PSF positions)");
   if (q->n < 1) return fail(GFC_EINVAL, "request needs at least one galaxy");
   if ((q->flags & ~7u) || ((q->flags & GFC_FORCE_FOURIER) && (q->flags & GFC_FORCE_REAL)))
     return fail(GFC_EINVAL, "bad flags");
