@@ -343,6 +343,28 @@ def size_throughput(gfc, ctx, dev, reps=5):
         res[cname] = dict(stamps=tot_n, ms=round(tot_ms, 4), stamps_per_s=round(tot_n / tot_ms * 1e3, 1))
         psf.close()
         mix.close()
+    # Lanczos-3 sub-pixel shift instead of the Fourier phase: the throughput workload
+    cfg = wl.config_metric()
+    g = cfg["gal"]
+    psf = gfc.Psf(ctx, cfg["psf"])
+    mix = gfc.Mixture.from_workload(ctx, cfg["mix"].as_f32())
+    d = lambda a: torch.as_tensor(a).to(dev)
+    args = [d(a) for a in (g.x, g.y, g.flux, g.r_e, g.e1, g.e2)]
+    out = torch.empty((len(g), 64, 64), dtype=torch.float32, device=dev)
+    for _ in range(3):
+        gfc.gfc_render_stamps(ctx, psf, mix, *args, 64, out=out, flags=gfc.GFC_SHIFT_LANCZOS3)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps * 4):
+        gfc.gfc_render_stamps(ctx, psf, mix, *args, 64, out=out, flags=gfc.GFC_SHIFT_LANCZOS3)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / (reps * 4)
+    res["lanczos3-dev8-64x64-100k"] = dict(stamps=len(g), ms=round(ms, 4), stamps_per_s=round(len(g) / ms * 1e3, 1))
+    del out
+    psf.close()
+    mix.close()
     # spatially varying PSF: 6 eigen components (degree-2 polynomial), 100k stamps at 64x64
     cfg = wl.config_eigen()
     g, e = cfg["gal"], cfg["eig"]

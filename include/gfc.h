@@ -68,7 +68,14 @@ typedef struct gfc_server gfc_server;
 enum {
   GFC_FORCE_FOURIER = 1, /* every component in Fourier space (w_i = 1) */
   GFC_FORCE_REAL = 2,    /* every component in real space (w_i = 0) */
-  GFC_RAMP_LINEAR = 4    /* linear ramp w_i = n_i - 3 instead of smoothstep */
+  GFC_RAMP_LINEAR = 4,   /* linear ramp w_i = n_i - 3 instead of smoothstep */
+  GFC_SHIFT_LANCZOS3 = 8 /* sub-pixel shift by Lanczos-3 interpolation of the finished
+                            stamp instead of the Fourier phase (step 8): the galaxy is
+                            rendered at (floor x, floor y), then the stamp, real-space
+                            terms included, is shifted by the fractional parts with the
+                            six normalised weights L(d + f), d = -3..2, L(t) = sinc(t)
+                            sinc(t/3), pixels outside the stamp taken as zero.  Forward
+                            only (the adjoint returns GFC_EUNSUPPORTED). */
 };
 
 const char* gfc_status_str(gfc_status s);

@@ -12,6 +12,7 @@ from ._lib import (  # noqa: F401
     GFC_FORCE_REAL,
     GFC_KMAX,
     GFC_RAMP_LINEAR,
+    GFC_SHIFT_LANCZOS3,
     GfcError,
     LIB_PATH,
     lib,

@@ -19,6 +19,7 @@ GFC_KMAX = 16
 GFC_FORCE_FOURIER = 1
 GFC_FORCE_REAL = 2
 GFC_RAMP_LINEAR = 4
+GFC_SHIFT_LANCZOS3 = 8
 
 STATUS = {
     0: "GFC_OK", -1: "GFC_EINVAL", -2: "GFC_EUNSUPPORTED", -3: "GFC_ENOMEM",

@@ -31,6 +31,7 @@ SOURCES = [
     "render_large.hip",
     "render_bwd.hip",
     "render_bwd_large.hip",
+    "lanczos.hip",
     "psf_fft.hip",
     "serve.cpp",
 ]

@@ -53,7 +53,7 @@ struct RenderArgs {
 constexpr int kEigMax = 16;     // eigen-PSF components
 constexpr int kEigDegMax = 3;   // polynomial degree
 
-enum : unsigned { kForceFourier = 1u, kForceReal = 2u, kRampLinear = 4u };
+enum : unsigned { kForceFourier = 1u, kForceReal = 2u, kRampLinear = 4u, kLanczos3 = 8u };
 
 // Per-galaxy state shared by every step.
 struct Galaxy {
@@ -88,6 +88,10 @@ __device__ __forceinline__ Galaxy load_galaxy(const RenderArgs& p, int64_t g) {
   // through every product of the Fourier and real-space paths.
   if (!G.ok) G.flux = __builtin_nanf("");
   const float fxf = floorf(G.x0), fyf = floorf(G.y0);
+  if (p.flags & kLanczos3) {  // rendered at the integer position; the stamp is shifted afterwards
+    G.x0 = fxf;
+    G.y0 = fyf;
+  }
   G.fx = G.ok ? G.x0 - fxf : 0.f;
   G.fy = G.ok ? G.y0 - fyf : 0.f;
   G.nx = G.ok ? ((int)(fxf - (float)W * floorf(fxf * (1.f / W)))) & (W - 1) : 0;

@@ -87,7 +87,7 @@ gfc_status fill_render_args(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix* mix, cons
   if (psf->ctx != ctx || mix->ctx != ctx) return fail(GFC_EINVAL, "handle belongs to another context");
   if (!stamp_size_ok(W)) return fail(GFC_EINVAL, "stamp size must be 16, 32, 64, 128 or 256");
   if (n < 0) return fail(GFC_EINVAL, "negative galaxy count");
-  if ((flags & ~7u) != 0) return fail(GFC_EINVAL, "unknown flag bits");
+  if ((flags & ~15u) != 0) return fail(GFC_EINVAL, "unknown flag bits");
   if ((flags & GFC_FORCE_FOURIER) && (flags & GFC_FORCE_REAL))
     return fail(GFC_EINVAL, "GFC_FORCE_FOURIER and GFC_FORCE_REAL are exclusive");
   if (n > 0 && (!gal->x || !gal->y || !gal->flux || !gal->r_e || !gal->e1 || !gal->e2))

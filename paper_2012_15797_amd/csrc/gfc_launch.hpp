@@ -22,6 +22,10 @@ hipError_t launch_render_w256(const RenderArgs& args, hipStream_t stream);
 hipError_t launch_bwd_w256(const RenderArgs& args, const float* gout, float* grad_params, float* amp_part,
                            hipStream_t stream);
 
+// Lanczos-3 shift of the finished stamps a.out by the fractional parts of
+// a.x, a.y (Section 2, step 8 alternative), in place.
+hipError_t launch_lanczos_shift(const RenderArgs& a, int W, hipStream_t stream);
+
 // PSF spectrum (Section 2, steps 1-2): separable float64 DFT of the S_y x S_x
 // PSF with its centre pixel at frequency-grid index 0.  Writes the
 // lane-permuted main columns, the Nyquist column and optionally the natural

@@ -15,6 +15,10 @@ gfc_status render_launch(const RenderArgs& a, int W, hipStream_t stream) {
     default: return fail(GFC_EINVAL, "unsupported stamp size");
   }
   if (e != hipSuccess) return hip_fail(e, "render launch");
+  if (a.flags & kLanczos3) {
+    e = launch_lanczos_shift(a, W, stream);
+    if (e != hipSuccess) return hip_fail(e, "Lanczos shift launch");
+  }
   return GFC_OK;
 }
 
