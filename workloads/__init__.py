@@ -17,6 +17,7 @@ from .generate import (  # noqa: F401
     exp6_table,
     dev8_table,
     mixture_set,
+    sersic_family,
     psf_double_gaussian,
     psf_moffat_halo,
     psf_single_gaussian_fit,
@@ -25,6 +26,8 @@ from .generate import (  # noqa: F401
     config1,
     config_metric,
     config_eigen,
+    config_sersic,
+    config_composite,
     config2,
     config3,
     config4_trace,

@@ -66,6 +66,27 @@ class Mixtures:
                         self.var.astype(np.float32).astype(np.float64))
 
 
+def sersic_family(K: int = 8, n_grid=None):
+    """Synthetic Sérsic mixture family: K components per grid index n whose
+    amplitudes (unit sum) and variances (r_e^2 units) vary smoothly with n,
+    shaped like the fitted families the paper describes (larger n: more
+    weight at both the smallest and the largest variances).  The fitted
+    tables of the paper are not available.  Returns dict(n_grid [S],
+    amp [S][K], var [S][K]) float32."""
+    n_grid = np.arange(0.5, 6.01, 0.5) if n_grid is None else np.asarray(n_grid, np.float64)
+    k = np.arange(K, dtype=np.float64)
+    amp, var = [], []
+    for n in n_grid:
+        lo = -2.0 - 0.45 * (n - 1.0)          # log10 of the smallest variance
+        hi = 0.15 + 0.11 * n                   # log10 of the largest variance
+        var.append(10.0 ** (lo + (hi - lo) * k / (K - 1)))
+        centre = (K - 1) * (0.62 - 0.05 * n)
+        width = 1.2 + 0.35 * n
+        a = np.exp(-0.5 * ((k - centre) / width) ** 2) + 0.02 * n * np.exp(-k)
+        amp.append(a / a.sum())
+    return dict(n_grid=n_grid.astype(np.float32), amp=np.array(amp, np.float32), var=np.array(var, np.float32))
+
+
 def mixture_set(tables) -> Mixtures:
     n = len(tables)
     K = np.zeros(n, np.int32)
@@ -283,6 +304,31 @@ def config_eigen(n=100_000):
     psf_y = rng.uniform(0.0, 4096.0, n).astype(np.float32)
     return dict(name="dev8-64x64-eigenpsf", mix=mix, eig=eigen_psf_moffat(64, 2), gal=gal,
                 psf_x=psf_x, psf_y=psf_y, flags=0)
+
+
+def config_sersic(n=100_000):
+    """General-Sérsic throughput workload: n galaxies in 64x64 stamps with the
+    metric workload's parameter distributions and a Sérsic index uniform on
+    [0.5, 6], rendered with the synthetic Sérsic family (K = 8)."""
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + 7))
+    gal = draw_galaxies(rng, n, 64, 0)
+    sersic_n = rng.uniform(0.5, 6.0, n).astype(np.float32)
+    return dict(name="sersic8-64x64-moffat", family=sersic_family(8), psf=_psf_b().astype(np.float32),
+                gal=gal, sersic_n=sersic_n, flags=0)
+
+
+def config_composite(n=100_000):
+    """Bulge + disk workload: EXP6 disks and DEV8 bulges sharing an
+    ellipticity, bulge fraction uniform on [0, 1], bulge-to-disk radius ratio
+    log-uniform on [0.2, 1]; 64x64 stamps."""
+    rng = np.random.Generator(np.random.PCG64(SEED_BASE + 8))
+    disk = exp6_table(rng)
+    bulge = dev8_table(rng)
+    gal = draw_galaxies(rng, n, 64, 0)
+    frac = rng.uniform(0.0, 1.0, n).astype(np.float32)
+    rho = _log_uniform(rng, 0.2, 1.0, n).astype(np.float32)
+    return dict(name="composite-exp6-dev8-64x64", mix=mixture_set([disk, bulge]), psf=_psf_b().astype(np.float32),
+                gal=gal, bulge_frac=frac, bulge_rho=rho, flags=0)
 
 
 def config2(n=100_000):
