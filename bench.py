@@ -365,6 +365,41 @@ def size_throughput(gfc, ctx, dev, reps=5):
     del out
     psf.close()
     mix.close()
+    # general Sersic (mixture interpolated per galaxy) and bulge + disk composites, 100k at 64x64
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps * 4):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / (reps * 4)
+
+    cfg = wl.config_sersic()
+    g = cfg["gal"]
+    psf = gfc.Psf(ctx, cfg["psf"])
+    fam = gfc.SersicFamily.from_workload(ctx, cfg["family"])
+    args = [d(a) for a in (g.x, g.y, g.flux, g.r_e, g.e1, g.e2)]
+    sn = d(cfg["sersic_n"])
+    out = torch.empty((len(g), 64, 64), dtype=torch.float32, device=dev)
+    ms = timed(lambda: gfc.gfc_render_stamps_sersic(ctx, psf, fam, *args, sn, 64, out=out))
+    res["sersic8-64x64-100k"] = dict(stamps=len(g), ms=round(ms, 4), stamps_per_s=round(len(g) / ms * 1e3, 1))
+    psf.close()
+    fam.close()
+    cfg = wl.config_composite()
+    g = cfg["gal"]
+    psf = gfc.Psf(ctx, cfg["psf"])
+    mix = gfc.Mixture.from_workload(ctx, cfg["mix"].as_f32())
+    args = [d(a) for a in (g.x, g.y, g.flux, g.r_e, g.e1, g.e2)]
+    fr, rh = d(cfg["bulge_frac"]), d(cfg["bulge_rho"])
+    ms = timed(lambda: gfc.gfc_render_stamps_composite(ctx, psf, mix, 0, 1, *args, fr, rh, 64, out=out))
+    res["composite14-64x64-100k"] = dict(stamps=len(g), ms=round(ms, 4), stamps_per_s=round(len(g) / ms * 1e3, 1))
+    del out
+    psf.close()
+    mix.close()
     # spatially varying PSF: 6 eigen components (degree-2 polynomial), 100k stamps at 64x64
     cfg = wl.config_eigen()
     g, e = cfg["gal"], cfg["eig"]

@@ -69,13 +69,18 @@ enum {
   GFC_FORCE_FOURIER = 1, /* every component in Fourier space (w_i = 1) */
   GFC_FORCE_REAL = 2,    /* every component in real space (w_i = 0) */
   GFC_RAMP_LINEAR = 4,   /* linear ramp w_i = n_i - 3 instead of smoothstep */
-  GFC_SHIFT_LANCZOS3 = 8 /* sub-pixel shift by Lanczos-3 interpolation of the finished
+  GFC_SHIFT_LANCZOS3 = 8, /* sub-pixel shift by Lanczos-3 interpolation of the finished
                             stamp instead of the Fourier phase (step 8): the galaxy is
                             rendered at (floor x, floor y), then the stamp, real-space
                             terms included, is shifted by the fractional parts with the
                             six normalised weights L(d + f), d = -3..2, L(t) = sinc(t)
                             sinc(t/3), pixels outside the stamp taken as zero.  Forward
                             only (the adjoint returns GFC_EUNSUPPORTED). */
+  GFC_ACCUMULATE = 16    /* add the rendered stamps to the values already in `out`
+                            instead of overwriting them (several galaxies in one
+                            stamp, e.g. a bulge and a disk with different shapes);
+                            not combinable with GFC_SHIFT_LANCZOS3 nor used by the
+                            server */
 };
 
 const char* gfc_status_str(gfc_status s);
@@ -184,6 +189,39 @@ typedef struct {
 gfc_status gfc_render_stamps(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix* mix,
                              const gfc_galaxies* gal, int64_t n, int W, unsigned flags,
                              float* out, void* hip_stream);
+
+/* ---------------------------------------------- Sersic and composite galaxies */
+/* A Sersic family (Section 1 profile family; closing discussion: mixture
+ * amplitudes and variances vary smoothly with the Sersic index, so tables
+ * fitted on a grid of indices are interpolated).  S (2..256) strictly
+ * increasing indices n_grid (host float32), each with K (1..16) components:
+ * amp, var host float32 [S][K] (var > 0, r_e^2 units).  Copied. */
+typedef struct gfc_sersic gfc_sersic;
+gfc_status gfc_sersic_create(gfc_ctx* ctx, int S, const float* n_grid, int K, const float* amp,
+                             const float* var, gfc_sersic** out);
+gfc_status gfc_sersic_destroy(gfc_sersic* fam);
+/* Forward render of general-Sersic galaxies: galaxy i uses the mixture
+ * interpolated piecewise-linearly in n between the two grid indices around
+ * sersic_n[i] (device float32 [n]), per component for amplitudes and
+ * variances.  sersic_n outside [n_grid[0], n_grid[S-1]] or not finite gives an
+ * invalid galaxy (NaN stamp, counted).  gal->mix_id must be NULL.  Otherwise
+ * as gfc_render_stamps; stream-ordered scratch of 136 bytes per galaxy. */
+gfc_status gfc_render_stamps_sersic(gfc_ctx* ctx, gfc_psf* psf, const gfc_sersic* fam,
+                                    const gfc_galaxies* gal, const float* sersic_n, int64_t n, int W,
+                                    unsigned flags, float* out, void* hip_stream);
+/* Forward render of bulge + disk galaxies sharing one ellipticity (Section 1,
+ * composite profiles): one mixture per galaxy made of the disk table's
+ * components with amplitudes (1 - f) A and the bulge table's with
+ * amplitudes f A and variances rho^2 v, f = bulge_frac[i] in [0, 1] and
+ * rho = bulge_rho[i] > 0 the bulge-to-disk r_e ratio (device float32 [n]);
+ * gal->r_e is the disk's.  The two tables together have at most 16
+ * components.  Out-of-range f or rho gives an invalid galaxy.  Bulges and
+ * disks with different ellipticities: two calls, the second with
+ * GFC_ACCUMULATE.  gal->mix_id must be NULL. */
+gfc_status gfc_render_stamps_composite(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix* mix, int disk_table,
+                                       int bulge_table, const gfc_galaxies* gal, const float* bulge_frac,
+                                       const float* bulge_rho, int64_t n, int W, unsigned flags,
+                                       float* out, void* hip_stream);
 
 /* Adjoint of gfc_render_stamps.  grad_out: device [n][W][W], the upstream
  * gradient dL/dI.  grad_params: device [n][6] float32 receiving

@@ -8,6 +8,7 @@ library is missing, loading it raises.
 """
 
 from ._lib import (  # noqa: F401
+    GFC_ACCUMULATE,
     GFC_FORCE_FOURIER,
     GFC_FORCE_REAL,
     GFC_KMAX,
@@ -21,8 +22,11 @@ from .api import (  # noqa: F401
     Context,
     Mixture,
     Psf,
+    SersicFamily,
     gfc_backward_workspace_bytes,
     gfc_render_stamps,
     gfc_render_stamps_backward,
+    gfc_render_stamps_composite,
+    gfc_render_stamps_sersic,
 )
 from .autograd import RenderStamps, render  # noqa: F401,E402

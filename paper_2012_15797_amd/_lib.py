@@ -20,6 +20,7 @@ GFC_FORCE_FOURIER = 1
 GFC_FORCE_REAL = 2
 GFC_RAMP_LINEAR = 4
 GFC_SHIFT_LANCZOS3 = 8
+GFC_ACCUMULATE = 16
 
 STATUS = {
     0: "GFC_OK", -1: "GFC_EINVAL", -2: "GFC_EUNSUPPORTED", -3: "GFC_ENOMEM",
@@ -79,6 +80,12 @@ PROTOTYPES = {
     "gfc_mix_set_amp": (I32, [P, P, P]),
     "gfc_mix_destroy": (I32, [P]),
     "gfc_render_stamps": (I32, [P, P, P, ctypes.POINTER(gfc_galaxies), I64, I32, U32, P, P]),
+    "gfc_sersic_create": (I32, [P, I32, ctypes.POINTER(ctypes.c_float), I32, ctypes.POINTER(ctypes.c_float),
+                                ctypes.POINTER(ctypes.c_float), PP]),
+    "gfc_sersic_destroy": (I32, [P]),
+    "gfc_render_stamps_sersic": (I32, [P, P, P, ctypes.POINTER(gfc_galaxies), P, I64, I32, U32, P, P]),
+    "gfc_render_stamps_composite": (I32, [P, P, P, I32, I32, ctypes.POINTER(gfc_galaxies), P, P, I64, I32, U32,
+                                          P, P]),
     "gfc_backward_workspace_bytes": (ctypes.c_size_t, [I64]),
     "gfc_render_stamps_backward": (I32, [P, P, P, ctypes.POINTER(gfc_galaxies), I64, I32, U32,
                                          P, P, P, P, P]),

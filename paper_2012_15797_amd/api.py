@@ -167,6 +167,34 @@ class Mixture:
             self.handle = None
 
 
+class SersicFamily:
+    """Mixture tables on a grid of Sersic indices (gfc_sersic_create):
+    n_grid [S] strictly increasing, amp and var [S, K]."""
+
+    def __init__(self, ctx: Context, n_grid, amp, var):
+        self.ctx = ctx
+        g = np.ascontiguousarray(n_grid, np.float32).reshape(-1)
+        a = np.ascontiguousarray(amp, np.float32)
+        v = np.ascontiguousarray(var, np.float32)
+        if a.shape != v.shape or a.ndim != 2 or a.shape[0] != g.shape[0]:
+            raise ValueError("amp and var must be [S, K] with S = len(n_grid)")
+        fp = ctypes.POINTER(ctypes.c_float)
+        h = ctypes.c_void_p()
+        call("gfc_sersic_create", ctx.handle, int(g.shape[0]), g.ctypes.data_as(fp), int(a.shape[1]),
+             a.ctypes.data_as(fp), v.ctypes.data_as(fp), ctypes.byref(h))
+        self.handle = h
+        self.K = a.shape[1]
+
+    @classmethod
+    def from_workload(cls, ctx, fam) -> "SersicFamily":
+        return cls(ctx, fam["n_grid"], fam["amp"], fam["var"])
+
+    def close(self):
+        if self.handle:
+            call("gfc_sersic_destroy", self.handle)
+            self.handle = None
+
+
 def _galaxies(dev, x, y, flux, r_e, e1, e2, mix_id, cd, psf_x=None, psf_y=None):
     ts = [_f32_dev(t, dev, nm) for t, nm in
           zip((x, y, flux, r_e, e1, e2), ("x", "y", "flux", "r_e", "e1", "e2"))]
@@ -212,6 +240,49 @@ def gfc_render_stamps(ctx, psf, mix, x, y, flux, r_e, e1, e2, W, mix_id=None, fl
     call("gfc_render_stamps", ctx.handle, psf.handle, mix.handle, ctypes.byref(g), int(n), int(W),
          int(flags), ctypes.c_void_p(out.data_ptr()), _stream_ptr(ctx.device))
     del keep
+    return out
+
+
+def _out_tensor(dev, n, W, out):
+    if out is None:
+        return torch.empty((n, W, W), dtype=torch.float32, device=dev)
+    if out.dtype != torch.float32 or not out.is_contiguous() or out.numel() != n * W * W:
+        raise ValueError("out must be a contiguous float32 tensor of n*W*W elements")
+    return out
+
+
+def gfc_render_stamps_sersic(ctx, psf, family, x, y, flux, r_e, e1, e2, sersic_n, W, flags=0, cd=None,
+                             out=None, psf_x=None, psf_y=None):
+    """General-Sersic render (gfc_render_stamps_sersic): each galaxy's mixture
+    is interpolated from `family` at its Sersic index."""
+    dev = ctx.torch_device
+    g, n, keep = _galaxies(dev, x, y, flux, r_e, e1, e2, None, cd, psf_x, psf_y)
+    sn = _f32_dev(sersic_n, dev, "sersic_n")
+    if sn.numel() != n:
+        raise ValueError("sersic_n length differs")
+    out = _out_tensor(dev, n, W, out)
+    call("gfc_render_stamps_sersic", ctx.handle, psf.handle, family.handle, ctypes.byref(g),
+         ctypes.c_void_p(sn.data_ptr()), int(n), int(W), int(flags), ctypes.c_void_p(out.data_ptr()),
+         _stream_ptr(ctx.device))
+    del keep, sn
+    return out
+
+
+def gfc_render_stamps_composite(ctx, psf, mix, disk_table, bulge_table, x, y, flux, r_e, e1, e2, bulge_frac,
+                                bulge_rho, W, flags=0, cd=None, out=None, psf_x=None, psf_y=None):
+    """Bulge + disk render with one ellipticity (gfc_render_stamps_composite);
+    r_e is the disk's, bulge_rho the bulge-to-disk radius ratio."""
+    dev = ctx.torch_device
+    g, n, keep = _galaxies(dev, x, y, flux, r_e, e1, e2, None, cd, psf_x, psf_y)
+    fr = _f32_dev(bulge_frac, dev, "bulge_frac")
+    rh = _f32_dev(bulge_rho, dev, "bulge_rho")
+    if fr.numel() != n or rh.numel() != n:
+        raise ValueError("bulge_frac/bulge_rho length differs")
+    out = _out_tensor(dev, n, W, out)
+    call("gfc_render_stamps_composite", ctx.handle, psf.handle, mix.handle, int(disk_table), int(bulge_table),
+         ctypes.byref(g), ctypes.c_void_p(fr.data_ptr()), ctypes.c_void_p(rh.data_ptr()), int(n), int(W),
+         int(flags), ctypes.c_void_p(out.data_ptr()), _stream_ptr(ctx.device))
+    del keep, fr, rh
     return out
 
 

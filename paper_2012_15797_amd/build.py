@@ -32,6 +32,7 @@ SOURCES = [
     "render_bwd.hip",
     "render_bwd_large.hip",
     "lanczos.hip",
+    "sersic.hip",
     "psf_fft.hip",
     "serve.cpp",
 ]

@@ -53,7 +53,7 @@ struct RenderArgs {
 constexpr int kEigMax = 16;     // eigen-PSF components
 constexpr int kEigDegMax = 3;   // polynomial degree
 
-enum : unsigned { kForceFourier = 1u, kForceReal = 2u, kRampLinear = 4u, kLanczos3 = 8u };
+enum : unsigned { kForceFourier = 1u, kForceReal = 2u, kRampLinear = 4u, kLanczos3 = 8u, kAccumulate = 16u };
 
 // Per-galaxy state shared by every step.
 struct Galaxy {

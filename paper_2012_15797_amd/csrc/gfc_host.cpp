@@ -87,7 +87,9 @@ gfc_status fill_render_args(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix* mix, cons
   if (psf->ctx != ctx || mix->ctx != ctx) return fail(GFC_EINVAL, "handle belongs to another context");
   if (!stamp_size_ok(W)) return fail(GFC_EINVAL, "stamp size must be 16, 32, 64, 128 or 256");
   if (n < 0) return fail(GFC_EINVAL, "negative galaxy count");
-  if ((flags & ~15u) != 0) return fail(GFC_EINVAL, "unknown flag bits");
+  if ((flags & ~31u) != 0) return fail(GFC_EINVAL, "unknown flag bits");
+  if ((flags & GFC_SHIFT_LANCZOS3) && (flags & GFC_ACCUMULATE))
+    return fail(GFC_EINVAL, "GFC_ACCUMULATE cannot be combined with GFC_SHIFT_LANCZOS3");
   if ((flags & GFC_FORCE_FOURIER) && (flags & GFC_FORCE_REAL))
     return fail(GFC_EINVAL, "GFC_FORCE_FOURIER and GFC_FORCE_REAL are exclusive");
   if (n > 0 && (!gal->x || !gal->y || !gal->flux || !gal->r_e || !gal->e1 || !gal->e2))
@@ -460,6 +462,7 @@ gfc_status gfc_mix_create(gfc_ctx* ctx, int n_tables, const int* K, const float*
   mix->ctx = ctx;
   mix->n_tables = n_tables;
   mix->kmax = kmax;
+  mix->K.assign(K, K + n_tables);
   const size_t nb = (size_t)n_tables * GFC_KMAX * sizeof(float);
   hipError_t e = hipMalloc(&mix->d_amp, nb);
   if (e == hipSuccess) e = hipMalloc(&mix->d_var, nb);

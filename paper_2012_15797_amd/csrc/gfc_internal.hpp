@@ -7,6 +7,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "gfc.h"
 #include "gfc_device.hpp"
@@ -49,6 +50,7 @@ struct gfc_mix {
   float* d_amp = nullptr;  // [n_tables][GFC_KMAX]
   float* d_var = nullptr;
   int32_t* d_K = nullptr;
+  std::vector<int32_t> K;  // host copy of the component counts
 };
 
 namespace gfc {

@@ -427,6 +427,7 @@ gfc_status gfc_render_stamps_backward(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix*
                                       void* hip_stream) {
   if (psf && psf->J > 0) return fail(GFC_EUNSUPPORTED, "the adjoint takes a constant PSF");
   if (flags & GFC_SHIFT_LANCZOS3) return fail(GFC_EUNSUPPORTED, "the adjoint uses the Fourier-phase shift");
+  if (flags & GFC_ACCUMULATE) return fail(GFC_EINVAL, "GFC_ACCUMULATE applies to forward renders");
   RenderArgs a;
   gfc_status st = fill_render_args(ctx, psf, mix, gal, n, W, flags, &a);
   if (st != GFC_OK) return st;

@@ -321,7 +321,8 @@ render_small_kernel(RenderArgs p) {
       static_for<0, C::HR>([&](auto rr) {
         constexpr int r = decltype(rr)::value;
         float* rowp = outp + ((ybase + r) & (W - 1)) * W;  // uniform when one stamp per wavefront
-        __builtin_nontemporal_store(val[r], &rowp[l]);     // streamed: this kernel never reads it back
+        const float v = (p.flags & kAccumulate) ? val[r] + rowp[l] : val[r];
+        __builtin_nontemporal_store(v, &rowp[l]);  // streamed output
       });
     }
     __syncthreads();

@@ -325,7 +325,8 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
     static_for<0, RPL>([&](auto rr) {
       constexpr int r = decltype(rr)::value;
       const int Y = (srow0 + r + G.ny) & (W - 1);
-      __builtin_nontemporal_store(val[r], &outp[Y * W + X]);  // streamed output
+      const float v = (p.flags & kAccumulate) ? val[r] + outp[Y * W + X] : val[r];
+      __builtin_nontemporal_store(v, &outp[Y * W + X]);  // streamed output
     });
     __syncthreads();
   }

@@ -455,7 +455,7 @@ gfc_status gfc_server_submit(gfc_server* s, const gfc_request* q, uint64_t* tick
   if (!stamp_size_ok(q->W)) return fail(GFC_EINVAL, "unsupported stamp size");
   if (q->psf->J > 0) return fail(GFC_EUNSUPPORTED, "requests take constant PSFs (no per-galaxy PSF positions)");
   if (q->n < 1) return fail(GFC_EINVAL, "request needs at least one galaxy");
-  if ((q->flags & ~15u) || ((q->flags & GFC_FORCE_FOURIER) && (q->flags & GFC_FORCE_REAL)))
+  if ((q->flags & ~15u) || ((q->flags & GFC_FORCE_FOURIER) && (q->flags & GFC_FORCE_REAL)))  // no GFC_ACCUMULATE
     return fail(GFC_EINVAL, "bad flags");
   if (!q->x || !q->y || !q->flux || !q->r_e || !q->e1 || !q->e2) return fail(GFC_EINVAL, "null parameter array");
   auto r = std::make_unique<Req>();
