@@ -36,8 +36,8 @@ struct BwdCfg {
   static constexpr int TN = W * (W + 2);      // floats per stamp
   static constexpr int CH = W <= 64 ? W : 32; // rows per load chunk
   static constexpr int NP = M + 5;            // evaluation points per lane
-  static constexpr int PB = M <= 16 ? NP : 16;  // points per block of the component loop
-  static constexpr int WPE = W <= 32 ? 4 : (W == 64 ? 3 : 1);  // occupancy target (waves per SIMD)
+  static constexpr int PB = M <= 16 ? NP : 8;   // points per block of the component loop
+  static constexpr int WPE = W == 16 ? 3 : (W <= 64 ? 2 : 1);  // occupancy target (waves per SIMD)
 };
 
 // Sum over the W lanes of one stamp; every lane of the stamp receives the total.
@@ -69,7 +69,6 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
   __shared__ float s_tile[C::SPB][C::TN];
   __shared__ float2 s_py[C::SPB][W + 2];
   __shared__ float2 s_nyq[C::SPB][W];
-  __shared__ float s_pk[C::SPB][kKmax][W];
   __shared__ float s_racc[C::SPB][kKmax][6];
   __shared__ float s_x2[2];
 
@@ -282,6 +281,7 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
       }
       ure[m] = u.x;
       uim[m] = u.y;
+      if constexpr (m % 8 == 7) __builtin_amdgcn_sched_barrier(0);  // bounds the PSF loads in flight
     });
     // Nyquist column, row l: h = 1, halved for the factor 2 in GN, and the
     // weight 1/2 of each of the nu = +-1/2 representatives
@@ -300,7 +300,10 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
 
   // ------------------------------------------------------------ component loop
   float ax = 0.f, ay = 0.f, a11 = 0.f, a12 = 0.f, a22 = 0.f;
-  for (int k = 0; k < kKmax; ++k) s_pk[slot][k][l] = 0.f;
+  // per-lane p_k partials [kKmax][W] in the g tile, which the column DFT has finished reading
+  float* s_pk = &s_tile[slot][0];
+  static_assert(kKmax * W <= C::TN, "p_k partials fit in the tile");
+  for (int k = 0; k < kKmax; ++k) s_pk[k * W + l] = 0.f;
   static_for<0, (NP + C::PB - 1) / C::PB>([&](auto bb) {
     constexpr int b0 = decltype(bb)::value * C::PB;
     constexpr int nb = (NP - b0) < C::PB ? (NP - b0) : C::PB;
@@ -329,7 +332,7 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
         S1[j] = fmaf(wav, e, S1[j]);
         pk = fmaf(ure[b0 + j], e, pk);
       });
-      s_pk[slot][k][l] += pk;
+      s_pk[k * W + l] += pk;
     }
     static_for<0, nb>([&](auto jj) {
       constexpr int j = decltype(jj)::value;
@@ -343,6 +346,9 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
       a12 = fmaf(n_ * o_, r1, a12);
       a22 = fmaf(o_ * o_, r1, a22);
     });
+    // Materialise the block's contribution here, so the compiler does not sink
+    // the accumulation (and keep this block's sums alive) past later blocks.
+    asm volatile("" : "+v"(ax), "+v"(ay), "+v"(a11), "+v"(a12), "+v"(a22));
   });
   ax = seg_sum<W>(ax, s_x2);
   ay = seg_sum<W>(ay, s_x2);
@@ -353,15 +359,17 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
   // p_k = sum over the stamp's lanes, fixed order; lane k of the stamp sums row k
   if (l < kKmax) {
     float acc = 0.f;
-    for (int i = 0; i < W; ++i) acc += s_pk[slot][l][i];
-    s_pk[slot][l][0] = acc;
+    for (int i = 0; i < W; ++i) acc += s_pk[l * W + i];
+    s_pk[l * W] = acc;
   }
   __syncthreads();
 
   // ------------------------------------------------------------ chain rule (lane 0)
-  if (l == 0 && live)
-    bwd_chain_rule<W>(p, G, gidx, rmask, ax, ay, a11, a12, a22, &s_pk[slot][0][0], W, &s_racc[slot][0][0],
+  if (l == 0 && live) {
+    Galaxy Gc = load_galaxy<W>(p, gidx);  // reloaded: keeps G's registers free in the loops above
+    bwd_chain_rule<W>(p, Gc, gidx, rmask, ax, ay, a11, a12, a22, s_pk, W, &s_racc[slot][0][0],
                       grad_params, amp_part);
+  }
 }
 
 // grad_amp[t][k] += sum over galaxies i with table t of amp_part[i][k], in

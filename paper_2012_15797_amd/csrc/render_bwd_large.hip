@@ -358,6 +358,9 @@ render_bwd_w256_kernel(RenderArgs p, const float* __restrict__ gout, float* __re
       a12 = fmaf(n_ * o_, r1, a12);
       a22 = fmaf(o_ * o_, r1, a22);
     });
+    // Materialise the block's contribution here, so the compiler does not sink
+    // the accumulation (and keep this block's sums alive) past later blocks.
+    asm volatile("" : "+v"(ax), "+v"(ay), "+v"(a11), "+v"(a12), "+v"(a22));
   });
   ax = block_sum512(ax, s_red);
   ay = block_sum512(ay, s_red);
