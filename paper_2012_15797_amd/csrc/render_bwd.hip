@@ -70,6 +70,7 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
   __shared__ float2 s_py[C::SPB][W + 2];
   __shared__ float2 s_nyq[C::SPB][W];
   __shared__ float s_racc[C::SPB][kKmax][6];
+  __shared__ float4 s_cmp[C::SPB][kKmax];  // per component: v, w A, w A v (zero when unused)
   __shared__ float s_x2[2];
 
   const int l = threadIdx.x % W;
@@ -85,6 +86,14 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
   const float* var = p.var + G.table * kKmax;
   const float trB = G.b11 + G.b22;
   const int kloop = (C::SPB == 1) ? G.K : p.kmax;
+
+  // per-component constants of the Fourier sums, computed once per stamp
+  if (l < kKmax) {
+    const float v = var[l];
+    const float A = (l < G.K) ? amp[l] : 0.f;
+    const float wa = route_weight<W>(v * trB, p.flags) * A;
+    s_cmp[slot][l] = make_float4(v, wa, wa * v, 0.f);
+  }
 
   // routing: components with a real-space share
   unsigned rmask = 0;
@@ -317,13 +326,11 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
       S1[j] = 0.f;
     });
     for (int k = 0; k < kloop; ++k) {
-      const float v = var[k];
-      const float A = (k < G.K) ? amp[k] : 0.f;
       // p_k is needed when w_k > 0 (amplitude and ramp terms); w_k = 0 means n_k <= 3,
       // where the ramp slope vanishes too
-      const float wa = route_weight<W>(v * trB, p.flags) * A;
+      const float4 cp = s_cmp[slot][k];
+      const float v = cp.x, wa = cp.y, wav = cp.z;
       if (wa == 0.f) continue;
-      const float wav = wa * v;
       float pk = 0.f;
       static_for<0, nb>([&](auto jj) {
         constexpr int j = decltype(jj)::value;
