@@ -130,13 +130,17 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
         const float nrm = kInv2Pi * __builtin_amdgcn_rsqf(det);
         float a0 = 0.f, ax = 0.f, ay = 0.f, axx = 0.f, axy = 0.f, ayy = 0.f;
         const float dy0 = (float)r0 - G.y0 - p.pg[1];
+        // per lane: z = S^-1 (dx, dy) = (cx + ixy dy, cy + iyy dy), and the log2 of
+        // nrm exp(-q/2) as e0 + dy (e1 + e2 dy), the normalisation folded in
+        const float cx = ixx * dx, cy = ixy * dx;
+        const float e0 = fmaf(kHalfLog2e * ixx, dx * dx, __builtin_amdgcn_logf(nrm));
+        const float e1 = 2.f * kHalfLog2e * cy, e2 = kHalfLog2e * iyy;
         static_for<0, C::CH>([&](auto rr) {
           constexpr int r = decltype(rr)::value;
           const float dy = dy0 + (float)r;
-          const float zx = fmaf(ixx, dx, ixy * dy);
-          const float zy = fmaf(ixy, dx, iyy * dy);
-          const float qf = fmaf(dx, zx, dy * zy);
-          const float gn = gv[r] * nrm * __builtin_amdgcn_exp2f(kHalfLog2e * qf);
+          const float zx = fmaf(ixy, dy, cx);
+          const float zy = fmaf(iyy, dy, cy);
+          const float gn = gv[r] * __builtin_amdgcn_exp2f(fmaf(dy, fmaf(e2, dy, e1), e0));
           const float gx = gn * zx, gy = gn * zy;
           a0 += gn;
           ax += gx;
