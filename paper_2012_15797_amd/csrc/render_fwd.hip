@@ -39,8 +39,10 @@ struct SmallCfg {
 // EIG: the PSF varies over the image (eigen-PSF components with polynomial
 // weights); its spectrum and Gaussian are formed per stamp from the
 // components' cached spectra and moments.
+// W = 128 is held to two wavefronts per SIMD (a small spill costs less than
+// running one wavefront per SIMD); the other sizes reach their occupancy freely.
 template <int W, bool EIG>
-__global__ void __launch_bounds__(SmallCfg<W>::BLOCK)
+__global__ void __launch_bounds__(SmallCfg<W>::BLOCK) __attribute__((amdgpu_waves_per_eu(W == 128 ? 2 : 1)))
 render_small_kernel(RenderArgs p) {
   using C = SmallCfg<W>;
   constexpr int M = C::M;
