@@ -96,12 +96,12 @@ def _composite_oracle(cfg, gal, frac, rho, idx, flags=0):
     return out
 
 
-@pytest.mark.parametrize("W", [32, 64, 128])
+@pytest.mark.parametrize("W", [16, 32, 64, 128, 256])
 def test_composite_each_size(ctx, W):
     import paper_2012_15797_amd as gfc
     cfg = wl.config_composite(10)
     rng = np.random.Generator(np.random.PCG64(1020 + W))
-    n = 30
+    n = 30 if W < 256 else 6
     gal = wl.draw_galaxies(rng, n, W, 0, r_e_range=(0.5, W / 5.0))
     frac = rng.uniform(0, 1, n).astype(np.float32)
     frac[:2] = [0.0, 1.0]
@@ -162,3 +162,35 @@ def test_profile_errors(ctx):
     with pytest.raises(gfc.GfcError):  # grid not increasing
         gfc.SersicFamily(ctx, [1.0, 1.0], np.ones((2, 3)), np.ones((2, 3)))
     psf.close(); mix.close(); big.close()
+
+
+def test_sersic_with_eigen_psf_and_lanczos(ctx):
+    """The profile, PSF and shift options compose: general Sersic galaxies
+    with a spatially varying PSF and the Lanczos shift, against the oracle
+    (eigen PSF at the position, Sersic mixture, Lanczos route)."""
+    import paper_2012_15797_amd as gfc
+    from oracle import eigen as oe
+    from oracle import lanczos as ol
+    rng = np.random.Generator(np.random.PCG64(1040))
+    fam = wl.sersic_family()
+    eig = wl.eigen_psf_moffat(64, 2)
+    n = 12
+    gal = wl.draw_galaxies(rng, n, 64, 0, r_e_range=(0.5, 6.0))
+    sn = rng.uniform(0.5, 6.0, n).astype(np.float32)
+    px = rng.uniform(0, 4096, n).astype(np.float32)
+    py = rng.uniform(0, 4096, n).astype(np.float32)
+    psf = gfc.Psf.eigen(ctx, eig["comps"], eig["coef"], eig["degree"], eig["norm"])
+    f = gfc.SersicFamily.from_workload(ctx, fam)
+    out = gfc.gfc_render_stamps_sersic(ctx, psf, f, gal.x, gal.y, gal.flux, gal.r_e, gal.e1, gal.e2, sn, 64,
+                                       flags=gfc.GFC_SHIFT_LANCZOS3, psf_x=px, psf_y=py)
+    gpu = _np(out)
+    comps = np.asarray(eig["comps"], np.float32).astype(np.float64)
+    ref = []
+    for i in range(n):
+        p = gal.params(i)
+        P = oe.eigen_psf_image(comps, eig["coef"], 2, eig["norm"], float(px[i]), float(py[i]))
+        a, v = osr.sersic_mixture(fam["n_grid"], fam["amp"], fam["var"], float(sn[i]))
+        ref.append(ol.render_stamp_lanczos(o.psf_spectrum(P, 64), o.psf_gauss_moments(P), a, v, p["x"], p["y"],
+                                           p["flux"], p["r_e"], p["e1"], p["e2"], 64))
+    _check(gpu, ref, list(range(n)))
+    psf.close(); f.close()
