@@ -375,18 +375,24 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
   }
   __syncthreads();
 
-  // ------------------------------------------------------------ chain rule (lane 0)
-  if (l == 0 && live) {
+  // ------------------------------------------------------------ chain rule
+  // lane k of the stamp takes component k; the terms are summed over 16 lanes
+  // and lane 0 finishes B -> (log r_e, e1, e2)
+  {
     Galaxy Gc = load_galaxy<W>(p, gidx);  // reloaded: keeps G's registers free in the loops above
-    bwd_chain_rule<W>(p, Gc, gidx, rmask, ax, ay, a11, a12, a22, s_pk, W, &s_racc[slot][0][0],
-                      grad_params, amp_part);
+    if constexpr (C::SPB == 1) make_uniform(Gc);
+    CompTerms t = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (live && l < kKmax)
+      t = bwd_component_terms<W>(p, Gc, l, rmask, s_pk, W, &s_racc[slot][0][0], amp_part + gidx * kKmax);
+    t = sum16(t);
+    if (l == 0 && live) bwd_chain_finish<W>(p, Gc, gidx, ax, ay, a11, a12, a22, t, grad_params);
   }
 }
 
 // grad_amp[t][k] += sum over galaxies i with table t of amp_part[i][k], in
 // index order within fixed 256-wide strides, then a fixed tree.
 __global__ void amp_grad_reduce(const float* __restrict__ amp_part, const int32_t* __restrict__ mix_id,
-                                int64_t n, int n_tables, float* __restrict__ grad_amp) {
+                                int64_t n, float* __restrict__ grad_amp) {
   const int t = blockIdx.x / kKmax, k = blockIdx.x % kKmax;
   __shared__ float s[256];
   float acc = 0.f;
@@ -477,7 +483,7 @@ gfc_status gfc_render_stamps_backward(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix*
   }
   if (e == hipSuccess && grad_amp) {
     hipLaunchKernelGGL(amp_grad_reduce, dim3(mix->n_tables * kKmax), dim3(256), 0, s, amp_part,
-                       gal->mix_id, n, mix->n_tables, grad_amp);
+                       gal->mix_id, n, grad_amp);
     e = hipGetLastError();
   }
   if (own) {

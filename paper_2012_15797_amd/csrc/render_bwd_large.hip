@@ -381,10 +381,14 @@ render_bwd_w256_kernel(RenderArgs p, const float* __restrict__ gout, float* __re
     s_pkw[l][0] = acc;
   }
   __syncthreads();
-  if (l == 0) {
+  if (wv == 0) {  // lanes 0..15 take one component each; lane 0 finishes
     Galaxy Gc = load_galaxy<W>(p, gidx);  // reloaded: keeps G's registers free in the loop above
-    bwd_chain_rule<W>(p, Gc, gidx, rmask, ax, ay, a11, a12, a22, &s_pkw[0][0], NWAVE, &s_racc[0][0],
-                      grad_params, amp_part);
+    make_uniform(Gc);
+    CompTerms t = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (l < kKmax)
+      t = bwd_component_terms<W>(p, Gc, l, rmask, &s_pkw[0][0], NWAVE, &s_racc[0][0], amp_part + gidx * kKmax);
+    t = sum16(t);
+    if (l == 0) bwd_chain_finish<W>(p, Gc, gidx, ax, ay, a11, a12, a22, t, grad_params);
   }
 }
 
