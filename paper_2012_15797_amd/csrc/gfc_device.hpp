@@ -165,6 +165,48 @@ __device__ __forceinline__ void eigen_gauss(const float (&mom)[6], float (&pg)[6
   pg[5] = F;
 }
 
+// (sin(pi r), cos(pi r)) for |r| < 2^22, without the special-value handling
+// of the library routine.  r = j/2 + f with j = rint(2 r) and |f| <= 1/4 (f is
+// exact); sin(pi f) and cos(pi f) are their Taylor series through f^9 and
+// f^10 (truncation below 2e-9 on |f| <= 1/4), and j mod 4 picks the quadrant.
+GFC_HD void sincospi_poly(float r, float* s_out, float* c_out) {
+  const float j = rintf(2.f * r);
+  const float f = fmaf(-0.5f, j, r);
+  const float f2 = f * f;
+  float sp = fmaf(f2, 0x1.5078340p-4f, -0x1.32d2ccp-1f);  // pi^9/9!, -pi^7/7!
+  sp = fmaf(f2, sp, 0x1.466bc6p+1f);                      // pi^5/5!
+  sp = fmaf(f2, sp, -0x1.4abbcep+2f);                     // -pi^3/3!
+  sp = fmaf(f2, sp, 0x1.921fb6p+1f) * f;                  // pi
+  float cp = fmaf(f2, -0x1.a6d1f2p-6f, 0x1.e1f506p-3f);   // -pi^10/10!, pi^8/8!
+  cp = fmaf(f2, cp, -0x1.55d3c8p+0f);                     // -pi^6/6!
+  cp = fmaf(f2, cp, 0x1.03c1f0p+2f);                      // pi^4/4!
+  cp = fmaf(f2, cp, -0x1.3bd3ccp+2f);                     // -pi^2/2!
+  cp = fmaf(f2, cp, 1.f);
+  const int q = (int)j;
+  const float s = (q & 1) ? cp : sp;
+  const float c = (q & 1) ? sp : cp;
+  *s_out = __builtin_bit_cast(float, __builtin_bit_cast(int, s) ^ ((q & 2) << 30));
+  *c_out = __builtin_bit_cast(float, __builtin_bit_cast(int, c) ^ (((q + 1) & 2) << 30));
+}
+
+// The value held by the even lane of this lane's pair (DPP quad permute
+// 0, 0, 2, 2).
+__device__ __forceinline__ float pair_even(float v) {
+  return __builtin_bit_cast(float,
+                            __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xA0, 0xF, 0xF, false));
+}
+
+// The value held by the second lane of this lane's stamp, for stamps of W
+// consecutive lanes (W >= 64: lane 1 of the wavefront).
+template <int W>
+__device__ __forceinline__ float stamp_lane1(float v) {
+  if constexpr (W >= 64) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 1));
+  } else {
+    return __shfl(v, ((int)__lane_id() & ~(W - 1)) + 1, 64);
+  }
+}
+
 // Step 4: Fourier weight of a component whose covariance trace is `tr`.
 template <int W>
 __device__ __forceinline__ float route_weight(float tr, unsigned flags) {

@@ -35,7 +35,7 @@ struct BwdCfg {
   static constexpr int TS = W + 2;            // floats per row of the g tile / float2 per row of Gr is W/2+1
   static constexpr int TN = W * (W + 2);      // floats per stamp
   static constexpr int CH = W <= 64 ? W : 32; // rows per load chunk
-  static constexpr int NP = M + 5;            // evaluation points per lane
+  static constexpr int NP = M + 3;            // evaluation points per lane
   static constexpr int PB = M <= 16 ? NP : 8;   // points per block of the component loop
   static constexpr int WPE = W == 16 ? 3 : (W <= 64 ? 2 : 1);  // occupancy target (waves per SIMD)
 };
@@ -240,20 +240,22 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
   // ------------------------------------------------------------ phases and U0 per point
   const float nu = (float)c * (1.f / W);
   const float hW = (float)h * (1.f / W);
-  float sx, cx;
-  sincospif(-2.f * G.fx * nu, &sx, &cx);
+  // Each lane evaluates the y phase of row l and one x phase (lanes h = 0:
+  // column c; lanes h = 1: nu = +1/2), as in the forward kernel.
   const float omN = (l < W / 2) ? (float)l * (1.f / W) : (l == W / 2 ? 0.5f : (float)(l - W) * (1.f / W));
-  float sy, cy, sym, cym, sxh, cxh;
-  sincospif(-2.f * G.fy * omN, &sy, &cy);
-  sincospif(G.fy, &sym, &cym);
-  sincospif(-G.fx, &sxh, &cxh);
+  float sy, cy, sxa, cxa;
+  sincospi_poly(-2.f * G.fy * omN, &sy, &cy);
+  sincospi_poly(h ? -G.fx : -2.f * G.fx * nu, &sxa, &cxa);
+  const float sx = pair_even(sxa), cx = pair_even(cxa);
+  const float sxh = stamp_lane1<W>(sxa), cxh = stamp_lane1<W>(cxa);
   s_py[slot][l] = make_float2(cy, sy);
-  if (l == 0) s_py[slot][W] = make_float2(cym, sym);
+  if (l == W / 2) s_py[slot][W] = make_float2(cy, -sy);  // omega = -1/2: conjugate of omega = +1/2
   __syncthreads();
 
   // Points: m = 0..M-1 (column c, row 2m+h), M (omega = -1/2 twin of the
-  // Nyquist row), M+1..M+4 (Nyquist column row l: nu = +-1/2, and the
-  // omega = -1/2 twins of the corner).  U0 already carries the Nyquist means.
+  // Nyquist row), M+1, M+2 (Nyquist column row l: nu = +-1/2).  U0 already
+  // carries the Nyquist means.  The corner's omega = -1/2 twins fold into
+  // M+1 and M+2 (see below).
   float ure[NP], uim[NP];
   // (nu, omega) of point j
   auto point = [&](auto jj, float& n_, float& o_) {
@@ -268,7 +270,7 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
       o_ = -0.5f;
     } else {
       n_ = (j - M) & 1 ? 0.5f : -0.5f;
-      o_ = j <= M + 2 ? omN : -0.5f;
+      o_ = omN;
     }
   };
   {
@@ -301,14 +303,17 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
     const float2 gamN = cscale(cmulc(p.psf_nyq[l], GN), 0.25f / ((float)W * (float)W));
     const bool corner = (l == W / 2);
     const float2 pyA = corner ? make_float2(0.5f * cy, 0.5f * sy) : make_float2(cy, sy);
-    const float2 pyB = corner ? make_float2(0.5f * cym, 0.5f * sym) : make_float2(0.f, 0.f);
+    const float2 pyB = corner ? make_float2(0.5f * cy, -0.5f * sy) : make_float2(0.f, 0.f);
     const float2 eM = make_float2(cxh, sxh), eP = make_float2(cxh, -sxh);
     const float2 u1 = cmul(cmul(gamN, eM), pyA), u2 = cmul(cmul(gamN, eP), pyA);
     const float2 u3 = cmul(cmul(gamN, eM), pyB), u4 = cmul(cmul(gamN, eP), pyB);
-    ure[M + 1] = u1.x; uim[M + 1] = u1.y;  // (+1/2, omN)
-    ure[M + 2] = u2.x; uim[M + 2] = u2.y;  // (-1/2, omN)
-    ure[M + 3] = u3.x; uim[M + 3] = u3.y;  // (+1/2, -1/2)
-    ure[M + 4] = u4.x; uim[M + 4] = u4.y;  // (-1/2, -1/2)
+    // The mixture transform is even, so at the corner (omN = +1/2) the twin
+    // (-1/2, -1/2) has the transform of (+1/2, +1/2) and (+1/2, -1/2) that of
+    // (-1/2, +1/2).  A twin's terms are those of its partner with (nu, omega)
+    // negated: its real part adds to the partner's, its imaginary part (which
+    // multiplies nu or omega) subtracts.  Elsewhere u3 = u4 = 0.
+    ure[M + 1] = u1.x + u4.x; uim[M + 1] = u1.y - u4.y;  // (+1/2, omN)
+    ure[M + 2] = u2.x + u3.x; uim[M + 2] = u2.y - u3.y;  // (-1/2, omN)
   }
 
   // ------------------------------------------------------------ component loop

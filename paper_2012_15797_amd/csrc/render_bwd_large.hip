@@ -33,7 +33,7 @@ constexpr int NWAVE = BLOCK / 64;
 constexpr int RCH = 64;             // rows per load chunk
 constexpr int TS = W + 1;           // floats per LDS tile row
 constexpr int SLAB = NC * W;        // float2 per stamp: [y][k_x], column 0 packed with k_x = 128
-constexpr int NP = M + 5;
+constexpr int NP = M + 3;
 constexpr int PB = 8;
 }  // namespace bigb
 
@@ -236,16 +236,15 @@ render_bwd_w256_kernel(RenderArgs p, const float* __restrict__ gout, float* __re
   const float nu = (float)c * (1.f / W);
   const float hW = (float)h * (1.f / W);
   float sx, cx;
-  sincospif(-2.f * G.fx * nu, &sx, &cx);
+  sincospi_poly(-2.f * G.fx * nu, &sx, &cx);
   const bool nyq_lane = l < W;
   const float omN = (l < W / 2) ? (float)l * (1.f / W) : (l == W / 2 ? 0.5f : (float)(l - W) * (1.f / W));
-  float sy = 0.f, cy = 1.f, sym, cym, sxh, cxh;
-  sincospif(G.fy, &sym, &cym);
-  sincospif(-G.fx, &sxh, &cxh);
+  float sy = 0.f, cy = 1.f, sxh, cxh;
+  sincospi_poly(-G.fx, &sxh, &cxh);
   if (nyq_lane) {
-    sincospif(-2.f * G.fy * omN, &sy, &cy);
+    sincospi_poly(-2.f * G.fy * omN, &sy, &cy);
     s_py[l] = make_float2(cy, sy);
-    if (l == 0) s_py[W] = make_float2(cym, sym);
+    if (l == W / 2) s_py[W] = make_float2(cy, -sy);  // omega = -1/2: conjugate of omega = +1/2
   }
   __syncthreads();
   float2 GN = make_float2(0.f, 0.f);
@@ -276,7 +275,7 @@ render_bwd_w256_kernel(RenderArgs p, const float* __restrict__ gout, float* __re
       o_ = -0.5f;
     } else {
       n_ = (j - M) & 1 ? 0.5f : -0.5f;
-      o_ = j <= M + 2 ? omN : -0.5f;
+      o_ = omN;
     }
   };
   {
@@ -305,14 +304,14 @@ render_bwd_w256_kernel(RenderArgs p, const float* __restrict__ gout, float* __re
                                  : make_float2(0.f, 0.f);
     const bool corner = (l == W / 2);
     const float2 pyA = corner ? make_float2(0.5f * cy, 0.5f * sy) : make_float2(cy, sy);
-    const float2 pyB = corner ? make_float2(0.5f * cym, 0.5f * sym) : make_float2(0.f, 0.f);
+    const float2 pyB = corner ? make_float2(0.5f * cy, -0.5f * sy) : make_float2(0.f, 0.f);
     const float2 eM = make_float2(cxh, sxh), eP = make_float2(cxh, -sxh);
     const float2 u1 = cmul(cmul(gamN, eM), pyA), u2 = cmul(cmul(gamN, eP), pyA);
     const float2 u3 = cmul(cmul(gamN, eM), pyB), u4 = cmul(cmul(gamN, eP), pyB);
-    ure[M + 1] = u1.x; uim[M + 1] = u1.y;
-    ure[M + 2] = u2.x; uim[M + 2] = u2.y;
-    ure[M + 3] = u3.x; uim[M + 3] = u3.y;
-    ure[M + 4] = u4.x; uim[M + 4] = u4.y;
+    // corner twins folded into their partners (the transform is even; see the
+    // W <= 128 adjoint)
+    ure[M + 1] = u1.x + u4.x; uim[M + 1] = u1.y - u4.y;
+    ure[M + 2] = u2.x + u3.x; uim[M + 2] = u2.y - u3.y;
   }
 
   // ------------------------------------------------------------ component loop

@@ -84,20 +84,20 @@ render_small_kernel(RenderArgs p) {
   });
   qv[M] = fmaf(-0.5f, fmaf(g2, -0.5f, g1), g0);  // Nyquist row, omega = -1/2
 
-  // Nyquist column k_x = W/2: lane l takes row k_y = l at nu = +1/2 and -1/2,
-  // and the omega = -1/2 twins of the corner bin.
+  // Nyquist column k_x = W/2: lane l takes row k_y = l at nu = +1/2 and -1/2.
+  // The corner's omega = -1/2 twins need no evaluation of their own: the
+  // mixture transform is even, so (+-1/2, -1/2) equals (-+1/2, +1/2), the
+  // pair that lane W/2 (omega = +1/2) holds.
   const float omN = (l < W / 2) ? (float)l * (1.f / W) : (l == W / 2 ? 0.5f : (float)(l - W) * (1.f / W));
   const float qa = kQ * G.b11 * 0.25f, qb = kQ * G.b12, qd = kQ * G.b22;
-  float qn[4];
+  float qn[2];
   qn[0] = fmaf(omN, fmaf(qd, omN, qb), qa);      // (+1/2, omN)
   qn[1] = fmaf(omN, fmaf(qd, omN, -qb), qa);     // (-1/2, omN)
-  qn[2] = fmaf(-0.5f, fmaf(qd, -0.5f, qb), qa);  // (+1/2, -1/2)
-  qn[3] = fmaf(-0.5f, fmaf(qd, -0.5f, -qb), qa); // (-1/2, -1/2)
 
   // Component 0 initialises the sums (every table has one; with zero Fourier
   // weight it contributes zeros), the rest accumulate.
   float S[M + 1];
-  float SN[4];
+  float SN[2];
   unsigned rmask = 0;  // components with a real-space share
   {
     const float v = var[0];
@@ -112,7 +112,7 @@ render_small_kernel(RenderArgs p) {
       constexpr int m = decltype(mm)::value;
       S[m] = wa * __builtin_amdgcn_exp2f(v * qv[m]);
     });
-    static_for<0, 4>([&](auto jj) {
+    static_for<0, 2>([&](auto jj) {
       constexpr int j = decltype(jj)::value;
       SN[j] = wa * __builtin_amdgcn_exp2f(v * qn[j]);
     });
@@ -131,7 +131,7 @@ render_small_kernel(RenderArgs p) {
       constexpr int m = decltype(mm)::value;
       S[m] = fmaf(wa, __builtin_amdgcn_exp2f(v * qv[m]), S[m]);
     });
-    static_for<0, 4>([&](auto jj) {
+    static_for<0, 2>([&](auto jj) {
       constexpr int j = decltype(jj)::value;
       SN[j] = fmaf(wa, __builtin_amdgcn_exp2f(v * qn[j]), SN[j]);
     });
@@ -181,25 +181,27 @@ render_small_kernel(RenderArgs p) {
   }
 
   // Fractional-shift phases (shift theorem): exp(-2 pi i (fx nu + fy om)).
-  float sx, cx;
-  sincospif(-2.f * G.fx * nu, &sx, &cx);
+  // Every lane evaluates the y phase of row l and one x phase: lanes h = 0
+  // that of column c, lanes h = 1 that of nu = +1/2 (the Nyquist column).
+  // The h = 1 lane of a pair takes its column's phase from its neighbour;
+  // omega = -1/2 is the conjugate of row W/2 (omega = +1/2).
+  float sy, cy;
+  sincospi_poly(-2.f * G.fy * omN, &sy, &cy);
+  float sxa, cxa;
+  sincospi_poly(h ? -G.fx : -2.f * G.fx * nu, &sxa, &cxa);
+  const float sx = pair_even(sxa), cx = pair_even(cxa);
+  const float sxh = stamp_lane1<W>(sxa), cxh = stamp_lane1<W>(cxa);  // nu = +1/2
   const float fs = G.flux * (1.f / ((float)W * (float)W));
   const float2 pxF = make_float2(fs * cx, fs * sx);
-  float sy, cy;
-  sincospif(-2.f * G.fy * omN, &sy, &cy);
-  float sym, cym;
-  sincospif(G.fy, &sym, &cym);  // omega = -1/2
   s_py[slot][l] = make_float2(cy, sy);
-  if (l == 0) s_py[slot][W] = make_float2(cym, sym);
+  if (l == W / 2) s_py[slot][W] = make_float2(cy, -sy);
   {
-    float sxh, cxh;
-    sincospif(-G.fx, &sxh, &cxh);  // nu = +1/2
     const float2 eM = make_float2(cxh, sxh), eP = make_float2(cxh, -sxh);
     const bool corner = (l == W / 2);
     const float2 pyA = corner ? make_float2(0.5f * cy, 0.5f * sy) : make_float2(cy, sy);
-    const float2 pyB = corner ? make_float2(0.5f * cym, 0.5f * sym) : make_float2(0.f, 0.f);
-    const float2 plus = cadd(cscale(pyA, SN[0]), cscale(pyB, SN[2]));
-    const float2 minus = cadd(cscale(pyA, SN[1]), cscale(pyB, SN[3]));
+    const float2 pyB = corner ? make_float2(0.5f * cy, -0.5f * sy) : make_float2(0.f, 0.f);
+    const float2 plus = cadd(cscale(pyA, SN[0]), cscale(pyB, SN[1]));
+    const float2 minus = cadd(cscale(pyA, SN[1]), cscale(pyB, SN[0]));
     const float2 inner = cadd(cmul(eM, plus), cmul(eP, minus));
     s_nyq[slot][l] = cmul(cscale(psfN, 0.5f * fs), inner);
   }
@@ -218,7 +220,7 @@ render_small_kernel(RenderArgs p) {
       Z[m] = cscale(cmul(cmul(P, s_py[slot][2 * m + h]), pxF), S[m]);
     }
   });
-  if (c == 0) {
+  if (c == 0) {  // column 0 carries the Nyquist column as its imaginary part
     static_for<0, M>([&](auto mm) {
       constexpr int m = decltype(mm)::value;
       const float2 xn = s_nyq[slot][2 * m + h];
@@ -285,10 +287,12 @@ render_small_kernel(RenderArgs p) {
   static_for<0, 2>([&](auto qq) {
     constexpr int q = decltype(qq)::value;
     if (y / C::HR == q) {
+      int row = (y - q * C::HR) * (W + 1);
+      asm volatile("" : "+v"(row));  // one base address; the 2n offsets stay immediate
       static_for<0, NC>([&](auto nn) {
         constexpr int n = decltype(nn)::value;
-        st[(y - q * C::HR) * (W + 1) + 2 * n] = R[n].x;
-        st[(y - q * C::HR) * (W + 1) + 2 * n + 1] = R[n].y;
+        st[row + 2 * n] = R[n].x;
+        st[row + 2 * n + 1] = R[n].y;
       });
     }
     __syncthreads();
@@ -299,33 +303,42 @@ render_small_kernel(RenderArgs p) {
     });
     const int ybase = (q * C::HR + G.ny) & (W - 1);  // output row of r = 0
     const int rwrap = W - ybase;                      // rows r >= rwrap wrap to the top
-    for (unsigned mk = rmask; mk != 0; mk &= mk - 1) {
-      const float2 rs = s_rs[slot][__builtin_ctz(mk)];  // LDS, not global: no wait on the stores above
-      const float v = rs.x, ra = rs.y;
-      const float sxx = fmaf(v, G.b11, pg[2]);
-      const float sxy = fmaf(v, G.b12, pg[3]);
-      const float syy = fmaf(v, G.b22, pg[4]);
-      const float det = fmaf(sxx, syy, -(sxy * sxy));
-      const float rdet = __builtin_amdgcn_rcpf(det);
-      const float ampr = ra * G.flux * pg[5] * kInv2Pi * __builtin_amdgcn_rsqf(det);
-      const float a0 = kHalfLog2e * (syy * rdet) * dx * dx;
-      const float a1 = -2.f * kHalfLog2e * (sxy * rdet) * dx;
-      const float a2 = kHalfLog2e * (sxx * rdet);
-      const float dyb = (float)ybase + dyc;
-      const float dybw = dyb - (float)W;
-      static_for<0, C::HR>([&](auto rr) {
-        constexpr int r = decltype(rr)::value;
-        const float dy = ((r >= rwrap) ? dybw : dyb) + (float)r;
-        val[r] = fmaf(ampr, __builtin_amdgcn_exp2f(fmaf(dy, fmaf(a2, dy, a1), a0)), val[r]);
-      });
+    if (rmask != 0) {
+      for (unsigned mk = rmask; mk != 0; mk &= mk - 1) {
+        const float2 rs = s_rs[slot][__builtin_ctz(mk)];  // LDS, not global: no wait on the stores above
+        const float v = rs.x, ra = rs.y;
+        const float sxx = fmaf(v, G.b11, pg[2]);
+        const float sxy = fmaf(v, G.b12, pg[3]);
+        const float syy = fmaf(v, G.b22, pg[4]);
+        const float det = fmaf(sxx, syy, -(sxy * sxy));
+        const float rdet = __builtin_amdgcn_rcpf(det);
+        const float ampr = ra * G.flux * pg[5] * kInv2Pi * __builtin_amdgcn_rsqf(det);
+        const float a0 = kHalfLog2e * (syy * rdet) * dx * dx;
+        const float a1 = -2.f * kHalfLog2e * (sxy * rdet) * dx;
+        const float a2 = kHalfLog2e * (sxx * rdet);
+        const float dyb = (float)ybase + dyc;
+        const float dybw = dyb - (float)W;
+        static_for<0, C::HR>([&](auto rr) {
+          constexpr int r = decltype(rr)::value;
+          const float dy = ((r >= rwrap) ? dybw : dyb) + (float)r;
+          val[r] = fmaf(ampr, __builtin_amdgcn_exp2f(fmaf(dy, fmaf(a2, dy, a1), a0)), val[r]);
+        });
+      }
     }
     if (live) {
-      static_for<0, C::HR>([&](auto rr) {
-        constexpr int r = decltype(rr)::value;
-        float* rowp = outp + ((ybase + r) & (W - 1)) * W;  // uniform when one stamp per wavefront
-        const float v = (p.flags & kAccumulate) ? val[r] + rowp[l] : val[r];
-        __builtin_nontemporal_store(v, &rowp[l]);  // streamed output
-      });
+      if (p.flags & kAccumulate) {
+        static_for<0, C::HR>([&](auto rr) {
+          constexpr int r = decltype(rr)::value;
+          float* rowp = outp + ((ybase + r) & (W - 1)) * W;
+          __builtin_nontemporal_store(val[r] + rowp[l], &rowp[l]);
+        });
+      } else {
+        static_for<0, C::HR>([&](auto rr) {
+          constexpr int r = decltype(rr)::value;
+          float* rowp = outp + ((ybase + r) & (W - 1)) * W;  // uniform when one stamp per wavefront
+          __builtin_nontemporal_store(val[r], &rowp[l]);     // streamed output
+        });
+      }
     }
     __syncthreads();
   });

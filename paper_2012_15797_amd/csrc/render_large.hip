@@ -79,14 +79,14 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
   const bool nyq_lane = l < W;  // lanes 0..255 also take one row of column k_x = 128
   const float omN = (l < W / 2) ? (float)l * (1.f / W) : (l == W / 2 ? 0.5f : (float)(l - W) * (1.f / W));
   const float qa = kQ * G.b11 * 0.25f, qb = kQ * G.b12, qd = kQ * G.b22;
-  float qn[4];
+  // (+1/2, omN) and (-1/2, omN).  The corner's omega = -1/2 twins equal
+  // the (-+1/2, +1/2) pair of lane W/2: the mixture transform is even.
+  float qn[2];
   qn[0] = fmaf(omN, fmaf(qd, omN, qb), qa);
   qn[1] = fmaf(omN, fmaf(qd, omN, -qb), qa);
-  qn[2] = fmaf(-0.5f, fmaf(qd, -0.5f, qb), qa);
-  qn[3] = fmaf(-0.5f, fmaf(qd, -0.5f, -qb), qa);
 
   float S[M + 1];
-  float SN[4] = {0.f, 0.f, 0.f, 0.f};
+  float SN[2] = {0.f, 0.f};
   static_for<0, M + 1>([&](auto mm) { S[decltype(mm)::value] = 0.f; });
   unsigned rmask = 0;
   for (int k = 0; k < G.K; ++k) {
@@ -104,7 +104,7 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
       S[m] = fmaf(wa, __builtin_amdgcn_exp2f(v * qv[m]), S[m]);
     });
     if (nyq_lane) {
-      static_for<0, 4>([&](auto jj) {
+      static_for<0, 2>([&](auto jj) {
         constexpr int j = decltype(jj)::value;
         SN[j] = fmaf(wa, __builtin_amdgcn_exp2f(v * qn[j]), SN[j]);
       });
@@ -140,22 +140,21 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
   }
 
   float sx, cx;
-  sincospif(-2.f * G.fx * nu, &sx, &cx);
+  sincospi_poly(-2.f * G.fx * nu, &sx, &cx);
   const float fs = G.flux * (1.f / ((float)W * (float)W));
   const float2 pxF = make_float2(fs * cx, fs * sx);
   if (nyq_lane) {
-    float sy, cy, sym, cym, sxh, cxh;
-    sincospif(-2.f * G.fy * omN, &sy, &cy);
-    sincospif(G.fy, &sym, &cym);
-    sincospif(-G.fx, &sxh, &cxh);
+    float sy, cy, sxh, cxh;
+    sincospi_poly(-2.f * G.fy * omN, &sy, &cy);
+    sincospi_poly(-G.fx, &sxh, &cxh);
     s_py[l] = make_float2(cy, sy);
-    if (l == 0) s_py[W] = make_float2(cym, sym);
+    if (l == W / 2) s_py[W] = make_float2(cy, -sy);  // omega = -1/2: conjugate of omega = +1/2
     const float2 eM = make_float2(cxh, sxh), eP = make_float2(cxh, -sxh);
     const bool corner = (l == W / 2);
     const float2 pyA = corner ? make_float2(0.5f * cy, 0.5f * sy) : make_float2(cy, sy);
-    const float2 pyB = corner ? make_float2(0.5f * cym, 0.5f * sym) : make_float2(0.f, 0.f);
-    const float2 plus = cadd(cscale(pyA, SN[0]), cscale(pyB, SN[2]));
-    const float2 minus = cadd(cscale(pyA, SN[1]), cscale(pyB, SN[3]));
+    const float2 pyB = corner ? make_float2(0.5f * cy, -0.5f * sy) : make_float2(0.f, 0.f);
+    const float2 plus = cadd(cscale(pyA, SN[0]), cscale(pyB, SN[1]));
+    const float2 minus = cadd(cscale(pyA, SN[1]), cscale(pyB, SN[0]));
     s_nyq[l] = cmul(cscale(psfN, 0.5f * fs), cadd(cmul(eM, plus), cmul(eP, minus)));
   }
   __syncthreads();
