@@ -24,11 +24,15 @@
 
 namespace gfc {
 
-template <int W>
+template <int W, bool EIG = false>
 struct SmallCfg {
   static constexpr int M = W / 2;                // values per lane in the column phase
-  static constexpr int BLOCK = W < 64 ? 64 : W;  // threads per workgroup
+  // With a varying PSF at 64 x 64, four stamps (one per wavefront) share a
+  // workgroup and stream each component spectrum through LDS once for all four.
+  static constexpr bool SHARE = EIG && W == 64;
+  static constexpr int BLOCK = SHARE ? 256 : (W < 64 ? 64 : W);  // threads per workgroup
   static constexpr int SPB = BLOCK / W;          // stamps per workgroup
+  static constexpr bool WAVE1 = W >= 64;         // one stamp per wavefront (or two wavefronts per stamp)
   // Both LDS transposes run in two passes over halves of the data, so a
   // stamp needs half the LDS and more wavefronts fit on a CU.
   static constexpr int T1S = W / 2 + 1;          // float2 per row: W/4 columns x 2 halves + pad
@@ -42,27 +46,28 @@ struct SmallCfg {
 // W = 128 is held to two wavefronts per SIMD (a small spill costs less than
 // running one wavefront per SIMD); the other sizes reach their occupancy freely.
 template <int W, bool EIG>
-__global__ void __launch_bounds__(SmallCfg<W>::BLOCK) __attribute__((amdgpu_waves_per_eu(W == 128 ? 2 : 1)))
+__global__ void __launch_bounds__((SmallCfg<W, EIG>::BLOCK)) __attribute__((amdgpu_waves_per_eu(W == 128 ? 2 : 1)))
 render_small_kernel(RenderArgs p) {
-  using C = SmallCfg<W>;
+  using C = SmallCfg<W, EIG>;
   constexpr int M = C::M;
   constexpr int T1S = C::T1S;
-  __shared__ float2 s_t1[C::SPB][C::T1N];
+  __shared__ __attribute__((aligned(16))) float2 s_t1[C::SPB][C::T1N];  // 16-byte aligned: also read as float4
   __shared__ float2 s_py[C::SPB][W + 2];
   __shared__ float2 s_nyq[C::SPB][W];
   __shared__ float2 s_rs[C::SPB][kKmax];  // (v, (1 - w) A) of the components with a real-space share
 
   const int l = (C::SPB == 1) ? (int)threadIdx.x : (int)threadIdx.x % W;
-  const int slot = (C::SPB == 1) ? 0 : (int)threadIdx.x / W;  // keeps the stamp index scalar
+  int slot = (C::SPB == 1) ? 0 : (int)threadIdx.x / W;
+  if constexpr (C::WAVE1 && C::SPB > 1) slot = __builtin_amdgcn_readfirstlane(slot);  // keeps the stamp index scalar
   const int64_t stamp = (int64_t)blockIdx.x * C::SPB + slot;
   const bool live = stamp < p.n;
   Galaxy G = load_galaxy<W>(p, live ? stamp : p.n - 1);
-  if constexpr (C::SPB == 1) {  // one stamp per wavefront: keep its integer shift in SGPRs
+  if constexpr (C::WAVE1) {  // one stamp per wavefront: keep its integer shift in SGPRs
     make_uniform(G);
   }
   const float* amp = p.amp + G.table * kKmax;
   const float* var = p.var + G.table * kKmax;
-  const int kloop = (C::SPB == 1) ? G.K : p.kmax;
+  const int kloop = C::WAVE1 ? G.K : p.kmax;
   const float trB = G.b11 + G.b22;
 
   // ---------------------------------------------------------------- column phase
@@ -147,7 +152,7 @@ render_small_kernel(RenderArgs p) {
     const int64_t g = live ? stamp : p.n - 1;
     float u = (p.psf_px[g] - p.eig_norm[0]) * p.eig_norm[1];
     float v = (p.psf_py[g] - p.eig_norm[2]) * p.eig_norm[3];
-    if constexpr (C::SPB == 1) {
+    if constexpr (C::WAVE1) {
       u = uniform_f(u);
       v = uniform_f(v);
     }
@@ -155,20 +160,67 @@ render_small_kernel(RenderArgs p) {
     static_for<0, M>([&](auto mm) { Pm[decltype(mm)::value] = make_float2(0.f, 0.f); });
     psfN = make_float2(0.f, 0.f);
     float mom[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int j = 0; j < p.eig_J; ++j) {
-      const float cj = eigen_weight(p, j, up, vp);
-      const float2* pj = p.psf_main + j * p.eig_stride;
-      static_for<0, M>([&](auto mm) {
-        constexpr int m = decltype(mm)::value;
-        const float2 q = pj[m * W + l];
-        Pm[m] = make_float2(fmaf(cj, q.x, Pm[m].x), fmaf(cj, q.y, Pm[m].y));
-      });
-      const float2 qn = p.psf_nyq[j * p.eig_stride + l];
-      psfN = make_float2(fmaf(cj, qn.x, psfN.x), fmaf(cj, qn.y, psfN.y));
-      static_for<0, 6>([&](auto ii) {
-        constexpr int i = decltype(ii)::value;
-        mom[i] = fmaf(cj, p.eig_mom[j * 6 + i], mom[i]);
-      });
+    if constexpr (C::SHARE) {
+      // Component j (its main bins, then its Nyquist column: contiguous in
+      // the cache) is copied into one half of the workgroup's transpose
+      // buffers, which are free until the column FFT, while the four
+      // wavefronts sum component j - 1 from the other half.  Reading a half
+      // again two components later is ordered by the barrier in between.
+      constexpr int NS = M * W + W;                   // float2 per component
+      constexpr int NV = NS / 2;                      // float4 per component
+      constexpr int PER = (NV + C::BLOCK - 1) / C::BLOCK;
+      static_assert(2 * NS <= C::SPB * C::T1N, "two component spectra fit in the transpose buffers");
+      float2* buf = &s_t1[0][0];
+      const float4* src = reinterpret_cast<const float4*>(p.psf_main);
+      const int64_t sv = p.eig_stride / 2;  // float4 from one component to the next
+      // staged float4 i of this thread: index threadIdx.x + i BLOCK, clamped
+      // (the last group is partial; clamped lanes re-read and skip the store)
+      float4 st0, st1, st2, st3, st4;
+      static_assert(PER == 5, "five float4 per thread at 64 x 64");
+      const int i4 = min((int)threadIdx.x + 4 * C::BLOCK, NV - 1);
+      const bool w4 = (int)threadIdx.x + 4 * C::BLOCK < NV;
+      const float4* s0 = src + threadIdx.x;
+      st0 = s0[0]; st1 = s0[C::BLOCK]; st2 = s0[2 * C::BLOCK]; st3 = s0[3 * C::BLOCK]; st4 = src[i4];
+      for (int j = 0; j < p.eig_J; ++j) {
+        float4* dst = reinterpret_cast<float4*>(buf + (j & 1) * NS) + threadIdx.x;
+        dst[0] = st0; dst[C::BLOCK] = st1; dst[2 * C::BLOCK] = st2; dst[3 * C::BLOCK] = st3;
+        if (w4) dst[4 * C::BLOCK] = st4;
+        __syncthreads();
+        if (j + 1 < p.eig_J) {  // in flight while component j is summed
+          const float4* sj = src + (j + 1) * sv;
+          st0 = sj[threadIdx.x]; st1 = sj[threadIdx.x + C::BLOCK]; st2 = sj[threadIdx.x + 2 * C::BLOCK];
+          st3 = sj[threadIdx.x + 3 * C::BLOCK]; st4 = sj[i4];
+        }
+        const float cj = eigen_weight(p, j, up, vp);
+        const float2* pj = buf + (j & 1) * NS;
+        static_for<0, M>([&](auto mm) {
+          constexpr int m = decltype(mm)::value;
+          const float2 q = pj[m * W + l];
+          Pm[m] = make_float2(fmaf(cj, q.x, Pm[m].x), fmaf(cj, q.y, Pm[m].y));
+        });
+        const float2 qn = pj[M * W + l];
+        psfN = make_float2(fmaf(cj, qn.x, psfN.x), fmaf(cj, qn.y, psfN.y));
+        static_for<0, 6>([&](auto ii) {
+          constexpr int i = decltype(ii)::value;
+          mom[i] = fmaf(cj, p.eig_mom[j * 6 + i], mom[i]);
+        });
+      }
+    } else {
+      for (int j = 0; j < p.eig_J; ++j) {
+        const float cj = eigen_weight(p, j, up, vp);
+        const float2* pj = p.psf_main + j * p.eig_stride;
+        static_for<0, M>([&](auto mm) {
+          constexpr int m = decltype(mm)::value;
+          const float2 q = pj[m * W + l];
+          Pm[m] = make_float2(fmaf(cj, q.x, Pm[m].x), fmaf(cj, q.y, Pm[m].y));
+        });
+        const float2 qn = p.psf_nyq[j * p.eig_stride + l];
+        psfN = make_float2(fmaf(cj, qn.x, psfN.x), fmaf(cj, qn.y, psfN.y));
+        static_for<0, 6>([&](auto ii) {
+          constexpr int i = decltype(ii)::value;
+          mom[i] = fmaf(cj, p.eig_mom[j * 6 + i], mom[i]);
+        });
+      }
     }
     eigen_gauss(mom, pg);
   } else {
@@ -345,9 +397,9 @@ render_small_kernel(RenderArgs p) {
   if (live && !G.ok && l == 0) atomicAdd(p.invalid, 1ull);
 }
 
-template <int W>
-hipError_t launch_render_small(const RenderArgs& args, hipStream_t stream) {
-  using C = SmallCfg<W>;
+template <int W, bool EIG>
+static hipError_t launch_small(const RenderArgs& args, hipStream_t stream) {
+  using C = SmallCfg<W, EIG>;
   constexpr int64_t kMaxBlocks = 1 << 30;
   RenderArgs p = args;
   int64_t done = 0;
@@ -365,15 +417,17 @@ hipError_t launch_render_small(const RenderArgs& args, hipStream_t stream) {
     p.psf_py = args.psf_py ? args.psf_py + done : nullptr;
     p.n = chunk;
     const unsigned blocks = (unsigned)((chunk + C::SPB - 1) / C::SPB);
-    if (args.eig_J > 0)
-      hipLaunchKernelGGL((render_small_kernel<W, true>), dim3(blocks), dim3(C::BLOCK), 0, stream, p);
-    else
-      hipLaunchKernelGGL((render_small_kernel<W, false>), dim3(blocks), dim3(C::BLOCK), 0, stream, p);
+    hipLaunchKernelGGL((render_small_kernel<W, EIG>), dim3(blocks), dim3(C::BLOCK), 0, stream, p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     done += chunk;
   }
   return hipSuccess;
+}
+
+template <int W>
+hipError_t launch_render_small(const RenderArgs& args, hipStream_t stream) {
+  return args.eig_J > 0 ? launch_small<W, true>(args, stream) : launch_small<W, false>(args, stream);
 }
 
 template hipError_t launch_render_small<16>(const RenderArgs&, hipStream_t);
