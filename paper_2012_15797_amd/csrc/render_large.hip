@@ -49,14 +49,19 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
   __shared__ float2 s_rs[kKmax];  // (v, (1 - w) A) of the components with a real-space share
   __shared__ float s_cj[kEigMax];  // eigen-PSF component weights at this galaxy's position
 
-  const int l = threadIdx.x;
-  const int64_t stamp = blockIdx.x;  // the launcher sizes the grid to the chunk exactly
+  // Persistent workgroups: one per CU, each with its own slab, which the
+  // next stamp reuses while it is still in L2 / the MALL.
+  float2* slab = scratch + (int64_t)blockIdx.x * SLAB;
+  for (int64_t stamp = blockIdx.x; stamp < p.n; stamp += gridDim.x) {
+  // The lane index is renewed opaquely each stamp, so lane-dependent values
+  // are recomputed per stamp instead of being held across the whole loop.
+  int l = threadIdx.x;
+  asm volatile("" : "+v"(l));
   Galaxy G = load_galaxy<W>(p, stamp);
   make_uniform(G);
   const float* amp = p.amp + G.table * kKmax;
   const float* var = p.var + G.table * kKmax;
   const float trB = G.b11 + G.b22;
-  float2* slab = scratch + (int64_t)blockIdx.x * SLAB;
 
   // ---------------------------------------------------------------- column phase
   const int c = l >> 2, h = l & 3;
@@ -192,11 +197,12 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
   fft<M, +1>(Z);
 
   // ---------------------------------------------------------------- combine
-  // X_c[y] = sum_h w^{h y} E_{h,c}[y mod 64],  w = exp(2 pi i / 256).
+  // X_c[j + 64 q] = sum_h i^{h q} w^{h j} E_{h,c}[j],  w = exp(2 pi i / 256):
+  // one radix-4 butterfly per (column, j) gives the four rows j + 64 q.
+  // Lane j of wavefront wv takes columns wv, wv + 8, wv + 16, wv + 24 of the chunk.
   {
-    const int yr = l >> 1, cp = l & 1;
-    const float2 w1 = twiddle_rt<+1, W>(yr), w2 = twiddle_rt<+1, W>(2 * yr), w3 = twiddle_rt<+1, W>(3 * yr);
-    const int j = yr & (M - 1);
+    const int j = l & (M - 1), wv = l >> 6;
+    const float2 w1 = twiddle_rt<+1, W>(j), w2 = twiddle_rt<+1, W>(2 * j), w3 = twiddle_rt<+1, W>(3 * j);
     for (int t = 0; t < NC / CCH; ++t) {
       if ((c / CCH) == t) {
         const int base = ((c % CCH) * D + h) * M;
@@ -206,21 +212,31 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
         });
       }
       __syncthreads();
-      for (int i = 0; i < CCH / 2; ++i) {
-        const int cl = 2 * i + cp;
+      static_for<0, CCH / (BLOCK / M)>([&](auto bb) {
+        constexpr int b = decltype(bb)::value;
+        const int cl = wv + b * (BLOCK / M);
         const float2* e = &s_buf[(cl * D) * M + j];
-        float2 x = e[0];
-        x = cadd(x, cmul(w1, e[M]));
-        x = cadd(x, cmul(w2, e[2 * M]));
-        x = cadd(x, cmul(w3, e[3 * M]));
+        const float2 t0 = e[0], t1 = cmul(w1, e[M]), t2 = cmul(w2, e[2 * M]), t3 = cmul(w3, e[3 * M]);
+        const float2 a = cadd(t0, t2), bq = csub(t0, t2), cq = cadd(t1, t3), d = rot90<+1>(csub(t1, t3));
+        const float2 x0 = cadd(a, cq), x1 = cadd(bq, d), x2 = csub(a, cq), x3 = csub(bq, d);
         const int cg = t * CCH + cl;
-        if (cg == 0) {
-          slab[yr] = make_float2(x.x, 0.f);
-          slab[NC * W + yr] = make_float2(x.y, 0.f);
+        if (cg == 0) {  // column 0 carries column 128 as its imaginary part
+          slab[j] = make_float2(x0.x, 0.f);
+          slab[j + 64] = make_float2(x1.x, 0.f);
+          slab[j + 128] = make_float2(x2.x, 0.f);
+          slab[j + 192] = make_float2(x3.x, 0.f);
+          slab[NC * W + j] = make_float2(x0.y, 0.f);
+          slab[NC * W + j + 64] = make_float2(x1.y, 0.f);
+          slab[NC * W + j + 128] = make_float2(x2.y, 0.f);
+          slab[NC * W + j + 192] = make_float2(x3.y, 0.f);
         } else {
-          slab[cg * W + yr] = x;
+          float2* o = slab + cg * W + j;
+          o[0] = x0;
+          o[64] = x1;
+          o[128] = x2;
+          o[192] = x3;
         }
-      }
+      });
       __syncthreads();
     }
   }
@@ -330,36 +346,26 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
     __syncthreads();
   }
   if (!G.ok && l == 0) atomicAdd(p.invalid, 1ull);
+  }  // stamps of this workgroup (the store loop ends with a barrier)
 }
 
 hipError_t launch_render_w256(const RenderArgs& args, hipStream_t stream) {
   using namespace big;
-  constexpr int64_t kChunk = 1024;  // stamps per launch (one scratch slab each)
-  const int64_t nb = std::min<int64_t>(args.n, kChunk);
-  float2* scratch = nullptr;
-  hipError_t e = hipMallocAsync((void**)&scratch, (size_t)nb * SLAB * sizeof(float2), stream);
+  // One workgroup per CU (the kernel's registers allow one 512-thread
+  // workgroup per CU), so the slabs in use total CUs x 264 KB.
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  RenderArgs p = args;
-  for (int64_t done = 0; done < args.n; done += kChunk) {
-    const int64_t chunk = std::min<int64_t>(args.n - done, kChunk);
-    p.x = args.x + done;
-    p.y = args.y + done;
-    p.flux = args.flux + done;
-    p.r_e = args.r_e + done;
-    p.e1 = args.e1 + done;
-    p.e2 = args.e2 + done;
-    p.mix_id = args.mix_id ? args.mix_id + done : nullptr;
-    p.out = args.out + done * (int64_t)W * W;
-    p.psf_px = args.psf_px ? args.psf_px + done : nullptr;
-    p.psf_py = args.psf_py ? args.psf_py + done : nullptr;
-    p.n = chunk;
-    if (args.eig_J > 0)
-      hipLaunchKernelGGL(render_w256_kernel<true>, dim3((unsigned)chunk), dim3(BLOCK), 0, stream, p, scratch);
-    else
-      hipLaunchKernelGGL(render_w256_kernel<false>, dim3((unsigned)chunk), dim3(BLOCK), 0, stream, p, scratch);
-    e = hipGetLastError();
-    if (e != hipSuccess) break;
-  }
+  const int64_t nb = std::min<int64_t>(args.n, std::max(cus, 1));
+  float2* scratch = nullptr;
+  e = hipMallocAsync((void**)&scratch, (size_t)nb * SLAB * sizeof(float2), stream);
+  if (e != hipSuccess) return e;
+  if (args.eig_J > 0)
+    hipLaunchKernelGGL(render_w256_kernel<true>, dim3((unsigned)nb), dim3(BLOCK), 0, stream, args, scratch);
+  else
+    hipLaunchKernelGGL(render_w256_kernel<false>, dim3((unsigned)nb), dim3(BLOCK), 0, stream, args, scratch);
+  e = hipGetLastError();
   hipError_t e2 = hipFreeAsync(scratch, stream);
   return e != hipSuccess ? e : e2;
 }
