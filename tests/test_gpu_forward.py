@@ -148,6 +148,32 @@ def test_large_galaxy_workload(ctx, W):
     psf.close(); mix.close()
 
 
+def test_large_workload_full_size_sampled(ctx):
+    """Every 256 x 256 stamp of the large-galaxy workload (about 9,900) in one
+    launch, as the benchmark times it: workgroups stay resident and take
+    several stamps each, one scratch slab per workgroup.  Stamps at the first
+    and later rounds of the workgroups, the last stamp and a random sample
+    against the oracle; every stamp finite."""
+    import torch
+    import paper_2012_15797_amd as gfc
+
+    cfg = wl.config3()
+    gal = cfg["gal"].subset(np.nonzero(cfg["gal"].W == 256)[0])
+    n = len(gal)
+    psf, mix = lib_objects(ctx, cfg)
+    out = gfc.gfc_render_stamps(ctx, psf, mix, gal.x, gal.y, gal.flux, gal.r_e, gal.e1, gal.e2, 256,
+                                mix_id=gal.mix_id)
+    torch.cuda.synchronize()
+    assert torch.isfinite(out).all()
+    rng = np.random.Generator(np.random.PCG64(11))
+    idx = sorted(set([0, 1, 255, 256, 257, 511, 512, 1023, 1024, n - 1]) |
+                 set(rng.choice(n, 14, replace=False).tolist()))
+    sample = out[torch.as_tensor(idx, device=out.device)].cpu().numpy().astype(np.float64)
+    errs = peak_errors(sample, oracle_stamps(cfg, gal, idx), list(range(len(idx))))
+    assert errs.max() <= TOL_PEAK, errs.max()
+    psf.close(); mix.close()
+
+
 @pytest.mark.parametrize("W", [64, 256])
 def test_edge_positions_and_integer_shift(ctx, W):
     """Centres near and across the stamp edge, negative and large
