@@ -207,6 +207,15 @@ __device__ __forceinline__ float stamp_lane1(float v) {
   }
 }
 
+// Raw Lanczos-3 value at t (exact zeros at the integers other than 0), for
+// the optional pixel-space sub-pixel shift (Section 2, step 8).
+__device__ __forceinline__ float lanczos3(float t) {
+  if (t == 0.f) return 1.f;
+  if (fabsf(t) >= 3.f || t == rintf(t)) return 0.f;
+  const float s = sinpif(t) * sinpif(t * (1.f / 3.f));
+  return s * (3.f * 0.10132118364233778f) / (t * t);  // sinc(t) sinc(t/3) = 3 sin(pi t) sin(pi t/3) / (pi t)^2
+}
+
 // Step 4: Fourier weight of a component whose covariance trace is `tr`.
 template <int W>
 __device__ __forceinline__ float route_weight(float tr, unsigned flags) {

@@ -19,14 +19,6 @@ namespace {
 
 constexpr int kThreads = 256;
 
-// Raw Lanczos-3 value at t (exact zeros at the integers other than 0).
-__device__ __forceinline__ float lanczos3(float t) {
-  if (t == 0.f) return 1.f;
-  if (fabsf(t) >= 3.f || t == rintf(t)) return 0.f;
-  const float s = sinpif(t) * sinpif(t * (1.f / 3.f));
-  return s * (3.f * 0.10132118364233778f) / (t * t);  // sinc(t) sinc(t/3) = 3 sin(pi t) sin(pi t/3) / (pi t)^2
-}
-
 // Fills w[0..5] (taps d = -3..2) for the fractional part of v; lanes 0..11 of
 // the block compute the raw values, every lane normalises.
 __device__ __forceinline__ void block_weights(float vx, float vy, float* s_w, float (&wx)[6], float (&wy)[6]) {

@@ -15,7 +15,7 @@ gfc_status render_launch(const RenderArgs& a, int W, hipStream_t stream) {
     default: return fail(GFC_EINVAL, "unsupported stamp size");
   }
   if (e != hipSuccess) return hip_fail(e, "render launch");
-  if (a.flags & kLanczos3) {
+  if ((a.flags & kLanczos3) && W > 64) {  // at W <= 64 the render kernel shifts while it stores
     e = launch_lanczos_shift(a, W, stream);
     if (e != hipSuccess) return hip_fail(e, "Lanczos shift launch");
   }

@@ -45,7 +45,8 @@ struct SmallCfg {
 // components' cached spectra and moments.
 // W = 128 is held to two wavefronts per SIMD (a small spill costs less than
 // running one wavefront per SIMD); the other sizes reach their occupancy freely.
-template <int W, bool EIG>
+// LZ (W <= 64): the Lanczos-3 sub-pixel shift is applied while storing.
+template <int W, bool EIG, bool LZ>
 __global__ void __launch_bounds__((SmallCfg<W, EIG>::BLOCK)) __attribute__((amdgpu_waves_per_eu(W == 128 ? 2 : 1)))
 render_small_kernel(RenderArgs p) {
   using C = SmallCfg<W, EIG>;
@@ -55,6 +56,7 @@ render_small_kernel(RenderArgs p) {
   __shared__ float2 s_py[C::SPB][W + 2];
   __shared__ float2 s_nyq[C::SPB][W];
   __shared__ float2 s_rs[C::SPB][kKmax];  // (v, (1 - w) A) of the components with a real-space share
+  __shared__ float s_lw[C::SPB][12];      // raw Lanczos weights of the stamp (fused shift, W <= 64)
 
   const int l = (C::SPB == 1) ? (int)threadIdx.x : (int)threadIdx.x % W;
   int slot = (C::SPB == 1) ? 0 : (int)threadIdx.x / W;
@@ -64,6 +66,35 @@ render_small_kernel(RenderArgs p) {
   Galaxy G = load_galaxy<W>(p, live ? stamp : p.n - 1);
   if constexpr (C::WAVE1) {  // one stamp per wavefront: keep its integer shift in SGPRs
     make_uniform(G);
+  }
+  // Lanczos-3 weights of the fused shift (taps d = -3..2 along x, then y),
+  // formed up front: with one stamp per wavefront they sit in scalar
+  // registers until the store.
+  float wxn[6], wy[6];
+  if constexpr (LZ) {
+    const int64_t gs = live ? stamp : p.n - 1;
+    if (l < 12) {  // raw weights of taps d = -3..2: x in 0..5, y in 6..11
+      const float v = l < 6 ? p.x[gs] : p.y[gs];
+      s_lw[slot][l] = lanczos3((float)((l % 6) - 3) + (v - floorf(v)));
+    }
+    float wx[6], sx = 0.f, sy = 0.f;  // (one wavefront per slot: no barrier needed)
+    static_for<0, 6>([&](auto dd) {
+      constexpr int d = decltype(dd)::value;
+      wx[d] = s_lw[slot][d];
+      wy[d] = s_lw[slot][6 + d];
+      sx += wx[d];
+      sy += wy[d];
+    });
+    const float rx = 1.f / sx, ry = 1.f / sy;
+    static_for<0, 6>([&](auto dd) {
+      constexpr int d = decltype(dd)::value;
+      wxn[d] = wx[d] * rx;
+      wy[d] *= ry;
+      if constexpr (C::WAVE1) {  // one stamp per wavefront: the weights are uniform
+        wxn[d] = uniform_f(wxn[d]);
+        wy[d] = uniform_f(wy[d]);
+      }
+    });
   }
   const float* amp = p.amp + G.table * kKmax;
   const float* var = p.var + G.table * kKmax;
@@ -336,68 +367,166 @@ render_small_kernel(RenderArgs p) {
   const float dyc = -G.y0 - pg[1];
   float* outp = p.out + (live ? stamp : 0) * (int64_t)(W * W);
   const int colsrc = (l - G.nx) & (W - 1);
-  static_for<0, 2>([&](auto qq) {
-    constexpr int q = decltype(qq)::value;
-    if (y / C::HR == q) {
-      int row = (y - q * C::HR) * (W + 1);
-      asm volatile("" : "+v"(row));  // one base address; the 2n offsets stay immediate
-      static_for<0, NC>([&](auto nn) {
-        constexpr int n = decltype(nn)::value;
-        st[row + 2 * n] = R[n].x;
-        st[row + 2 * n + 1] = R[n].y;
-      });
-    }
-    __syncthreads();
-    float val[C::HR];
-    static_for<0, C::HR>([&](auto rr) {
-      constexpr int r = decltype(rr)::value;
-      val[r] = st[r * (W + 1) + colsrc];
-    });
-    const int ybase = (q * C::HR + G.ny) & (W - 1);  // output row of r = 0
-    const int rwrap = W - ybase;                      // rows r >= rwrap wrap to the top
-    if (rmask != 0) {
-      for (unsigned mk = rmask; mk != 0; mk &= mk - 1) {
-        const float2 rs = s_rs[slot][__builtin_ctz(mk)];  // LDS, not global: no wait on the stores above
-        const float v = rs.x, ra = rs.y;
-        const float sxx = fmaf(v, G.b11, pg[2]);
-        const float sxy = fmaf(v, G.b12, pg[3]);
-        const float syy = fmaf(v, G.b22, pg[4]);
-        const float det = fmaf(sxx, syy, -(sxy * sxy));
-        const float rdet = __builtin_amdgcn_rcpf(det);
-        const float ampr = ra * G.flux * pg[5] * kInv2Pi * __builtin_amdgcn_rsqf(det);
-        const float a0 = kHalfLog2e * (syy * rdet) * dx * dx;
-        const float a1 = -2.f * kHalfLog2e * (sxy * rdet) * dx;
-        const float a2 = kHalfLog2e * (sxx * rdet);
+  if constexpr (LZ) {
+    static_assert(W <= 64, "the fused shift keeps a whole column per lane");
+    {
+      // Lanczos-3 shift by the fractional position, fused into the store: a
+      // lane keeps its whole output column (W <= 64), so the stamp makes one
+      // trip to memory.  The real-space components are added to the rows
+      // first (the shift applies to the whole stamp), the rows are filtered
+      // along x while read from the LDS tile, the columns along y in
+      // registers.  Taps outside the stamp have weight zero.
+      if (rmask != 0) {
+        // Real-space components along this lane's tile row y, with exactly the
+        // arithmetic of the column-wise store (so that at integer positions,
+        // where the shift is the identity, both routes agree bit for bit).
+        const int yq = y / C::HR, yr = y - yq * C::HR;
+        const int ybase = (yq * C::HR + G.ny) & (W - 1);
         const float dyb = (float)ybase + dyc;
-        const float dybw = dyb - (float)W;
+        const float dy = ((yr >= W - ybase) ? dyb - (float)W : dyb) + (float)yr;
+        for (unsigned mk = rmask; mk != 0; mk &= mk - 1) {
+          const float2 rs = s_rs[slot][__builtin_ctz(mk)];
+          const float v = rs.x, ra = rs.y;
+          const float sxx = fmaf(v, G.b11, pg[2]);
+          const float sxy = fmaf(v, G.b12, pg[3]);
+          const float syy = fmaf(v, G.b22, pg[4]);
+          const float det = fmaf(sxx, syy, -(sxy * sxy));
+          const float rdet = __builtin_amdgcn_rcpf(det);
+          const float ampr = ra * G.flux * pg[5] * kInv2Pi * __builtin_amdgcn_rsqf(det);
+          const float c0 = kHalfLog2e * (syy * rdet);
+          const float c1 = -2.f * kHalfLog2e * (sxy * rdet);
+          const float a2 = kHalfLog2e * (sxx * rdet);
+          int nxc = G.nx;  // renewed per component: the columns' dx are recomputed rather than all held
+          if constexpr (C::WAVE1) asm volatile("" : "+s"(nxc));
+          else asm volatile("" : "+v"(nxc));
+          static_for<0, W>([&](auto xx) {
+            constexpr int x = decltype(xx)::value;
+            const float dxp = (float)((x + nxc) & (W - 1)) - G.x0 - pg[0];  // output column's dx
+            const float e = fmaf(dy, fmaf(a2, dy, c1 * dxp), c0 * dxp * dxp);
+            if constexpr (x & 1) R[x >> 1].y = fmaf(ampr, __builtin_amdgcn_exp2f(e), R[x >> 1].y);
+            else R[x >> 1].x = fmaf(ampr, __builtin_amdgcn_exp2f(e), R[x >> 1].x);
+          });
+        }
+      }
+      // Rows: the x filter in the row-owning lane (tile column x is output
+      // column (x + nx) mod W, so neighbours are cyclic in x, masked where
+      // they cross the stamp's edge), written to the LDS tile.  Columns: the
+      // y filter as the tile's rows are read, each source row added into the
+      // output rows it feeds.
+      float acc[W];
+      static_for<0, W>([&](auto tt) { acc[decltype(tt)::value] = 0.f; });
+      static_for<0, 2>([&](auto qq) {
+        constexpr int q = decltype(qq)::value;
+        if (y / C::HR == q) {
+          int row = (y - q * C::HR) * (W + 1);
+          asm volatile("" : "+v"(row));
+          static_for<0, W>([&](auto xx) {
+            constexpr int x = decltype(xx)::value;
+            const int X = (x + G.nx) & (W - 1);
+            float hsum = 0.f;
+            static_for<0, 6>([&](auto dd) {
+              constexpr int d = decltype(dd)::value;
+              constexpr int xs = (x + d - 3) & (W - 1);
+              const float in = (xs & 1) ? R[xs >> 1].y : R[xs >> 1].x;
+              const int Xs = X + d - 3;
+              hsum = fmaf((Xs >= 0 && Xs < W) ? wxn[d] : 0.f, in, hsum);
+            });
+            st[row + x] = hsum;
+          });
+        }
+        __syncthreads();
         static_for<0, C::HR>([&](auto rr) {
-          constexpr int r = decltype(rr)::value;
-          const float dy = ((r >= rwrap) ? dybw : dyb) + (float)r;
-          val[r] = fmaf(ampr, __builtin_amdgcn_exp2f(fmaf(dy, fmaf(a2, dy, a1), a0)), val[r]);
+          constexpr int sr = q * C::HR + decltype(rr)::value;  // source tile row
+          const float v = st[(sr - q * C::HR) * (W + 1) + colsrc];
+          static_for<0, 6>([&](auto dd) {
+            constexpr int d = decltype(dd)::value;
+            constexpr int t = (sr - d + 3 + W) & (W - 1);  // output tile row fed through tap d
+            const int ys = ((t + G.ny) & (W - 1)) + d - 3;
+            acc[t] = fmaf((ys >= 0 && ys < W) ? wy[d] : 0.f, v, acc[t]);
+          });
+          // Output row t is complete once its sources t - 3 .. t + 2 are in:
+          // rows 3 .. W/2 - 3 during the first pass, rows W/2 - 2 .. W - 3
+          // during the second, and rows W - 2, W - 1, 0, 1, 2 (whose sources
+          // wrap around) at the end.
+          constexpr int done = sr - 2;
+          if constexpr ((q == 0 && done >= 3) || q == 1) {
+            if (live) __builtin_nontemporal_store(acc[done], outp + ((done + G.ny) & (W - 1)) * W + l);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        });
+        __syncthreads();
+      });
+      if (live) {
+        static_for<0, 5>([&](auto ii) {
+          constexpr int t = (W - 2 + decltype(ii)::value) & (W - 1);
+          __builtin_nontemporal_store(acc[t], outp + ((t + G.ny) & (W - 1)) * W + l);
         });
       }
     }
-    if (live) {
-      if (p.flags & kAccumulate) {
-        static_for<0, C::HR>([&](auto rr) {
-          constexpr int r = decltype(rr)::value;
-          float* rowp = outp + ((ybase + r) & (W - 1)) * W;
-          __builtin_nontemporal_store(val[r] + rowp[l], &rowp[l]);
-        });
-      } else {
-        static_for<0, C::HR>([&](auto rr) {
-          constexpr int r = decltype(rr)::value;
-          float* rowp = outp + ((ybase + r) & (W - 1)) * W;  // uniform when one stamp per wavefront
-          __builtin_nontemporal_store(val[r], &rowp[l]);     // streamed output
+  } else {
+    static_for<0, 2>([&](auto qq) {
+      constexpr int q = decltype(qq)::value;
+      if (y / C::HR == q) {
+        int row = (y - q * C::HR) * (W + 1);
+        asm volatile("" : "+v"(row));  // one base address; the 2n offsets stay immediate
+        static_for<0, NC>([&](auto nn) {
+          constexpr int n = decltype(nn)::value;
+          st[row + 2 * n] = R[n].x;
+          st[row + 2 * n + 1] = R[n].y;
         });
       }
-    }
-    __syncthreads();
-  });
+      __syncthreads();
+      float val[C::HR];
+      static_for<0, C::HR>([&](auto rr) {
+        constexpr int r = decltype(rr)::value;
+        val[r] = st[r * (W + 1) + colsrc];
+      });
+      const int ybase = (q * C::HR + G.ny) & (W - 1);  // output row of r = 0
+      const int rwrap = W - ybase;                      // rows r >= rwrap wrap to the top
+      if (rmask != 0) {
+        for (unsigned mk = rmask; mk != 0; mk &= mk - 1) {
+          const float2 rs = s_rs[slot][__builtin_ctz(mk)];  // LDS, not global: no wait on the stores above
+          const float v = rs.x, ra = rs.y;
+          const float sxx = fmaf(v, G.b11, pg[2]);
+          const float sxy = fmaf(v, G.b12, pg[3]);
+          const float syy = fmaf(v, G.b22, pg[4]);
+          const float det = fmaf(sxx, syy, -(sxy * sxy));
+          const float rdet = __builtin_amdgcn_rcpf(det);
+          const float ampr = ra * G.flux * pg[5] * kInv2Pi * __builtin_amdgcn_rsqf(det);
+          const float a0 = kHalfLog2e * (syy * rdet) * dx * dx;
+          const float a1 = -2.f * kHalfLog2e * (sxy * rdet) * dx;
+          const float a2 = kHalfLog2e * (sxx * rdet);
+          const float dyb = (float)ybase + dyc;
+          const float dybw = dyb - (float)W;
+          static_for<0, C::HR>([&](auto rr) {
+            constexpr int r = decltype(rr)::value;
+            const float dy = ((r >= rwrap) ? dybw : dyb) + (float)r;
+            val[r] = fmaf(ampr, __builtin_amdgcn_exp2f(fmaf(dy, fmaf(a2, dy, a1), a0)), val[r]);
+          });
+        }
+      }
+      if (live) {
+        if (p.flags & kAccumulate) {
+          static_for<0, C::HR>([&](auto rr) {
+            constexpr int r = decltype(rr)::value;
+            float* rowp = outp + ((ybase + r) & (W - 1)) * W;
+            __builtin_nontemporal_store(val[r] + rowp[l], &rowp[l]);
+          });
+        } else {
+          static_for<0, C::HR>([&](auto rr) {
+            constexpr int r = decltype(rr)::value;
+            float* rowp = outp + ((ybase + r) & (W - 1)) * W;  // uniform when one stamp per wavefront
+            __builtin_nontemporal_store(val[r], &rowp[l]);     // streamed output
+          });
+        }
+      }
+      __syncthreads();
+    });
+  }
   if (live && !G.ok && l == 0) atomicAdd(p.invalid, 1ull);
 }
 
-template <int W, bool EIG>
+template <int W, bool EIG, bool LZ>
 static hipError_t launch_small(const RenderArgs& args, hipStream_t stream) {
   using C = SmallCfg<W, EIG>;
   constexpr int64_t kMaxBlocks = 1 << 30;
@@ -417,7 +546,7 @@ static hipError_t launch_small(const RenderArgs& args, hipStream_t stream) {
     p.psf_py = args.psf_py ? args.psf_py + done : nullptr;
     p.n = chunk;
     const unsigned blocks = (unsigned)((chunk + C::SPB - 1) / C::SPB);
-    hipLaunchKernelGGL((render_small_kernel<W, EIG>), dim3(blocks), dim3(C::BLOCK), 0, stream, p);
+    hipLaunchKernelGGL((render_small_kernel<W, EIG, LZ>), dim3(blocks), dim3(C::BLOCK), 0, stream, p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     done += chunk;
@@ -427,7 +556,11 @@ static hipError_t launch_small(const RenderArgs& args, hipStream_t stream) {
 
 template <int W>
 hipError_t launch_render_small(const RenderArgs& args, hipStream_t stream) {
-  return args.eig_J > 0 ? launch_small<W, true>(args, stream) : launch_small<W, false>(args, stream);
+  if constexpr (W <= 64) {
+    if (args.flags & kLanczos3)
+      return args.eig_J > 0 ? launch_small<W, true, true>(args, stream) : launch_small<W, false, true>(args, stream);
+  }
+  return args.eig_J > 0 ? launch_small<W, true, false>(args, stream) : launch_small<W, false, false>(args, stream);
 }
 
 template hipError_t launch_render_small<16>(const RenderArgs&, hipStream_t);
