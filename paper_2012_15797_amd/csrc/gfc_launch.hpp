@@ -23,7 +23,8 @@ hipError_t launch_bwd_w256(const RenderArgs& args, const float* gout, float* gra
                            hipStream_t stream);
 
 // Lanczos-3 shift of the finished stamps a.out by the fractional parts of
-// a.x, a.y (Section 2, step 8 alternative), in place.
+// a.x, a.y (Section 2, step 8 alternative), in place; W = 128 or 256 (the
+// smaller sizes shift inside the render kernel).
 hipError_t launch_lanczos_shift(const RenderArgs& a, int W, hipStream_t stream);
 
 // PSF spectrum (Section 2, steps 1-2): separable float64 DFT of the S_y x S_x

@@ -7,9 +7,11 @@
 //   w[d] = L(d + f) / sum_d' L(d' + f),  L(t) = sinc(t) sinc(t / 3) on |t| < 3,
 // with pixels outside the stamp taken as zero.  Separable: rows, then columns.
 //
-// W <= 128: one workgroup per stamp, the stamp held in LDS, both passes in
-// place, one read and one write of the stamp.  W = 256 (256 KB per stamp):
-// a row-band pass and a column-band pass, each in place through LDS.
+// These passes serve W = 128 and 256 (up to 64 x 64 the render kernel
+// applies the same filter while it stores).  W = 128: one workgroup per
+// stamp, the stamp held in LDS, both passes in place, one read and one write
+// of the stamp.  W = 256 (256 KB per stamp): a row-band pass and a
+// column-band pass, each in place through LDS.
 #include "gfc_internal.hpp"
 #include "gfc_launch.hpp"
 
@@ -168,9 +170,6 @@ hipError_t launch_lanczos_shift(const RenderArgs& a, int W, hipStream_t stream) 
     float* o = a.out + done * (int64_t)W * W;
     const dim3 grid((unsigned)(chunk * per)), block(kThreads);
     switch (W) {
-      case 16: hipLaunchKernelGGL(lanczos_tile_kernel<16>, grid, block, 0, stream, x, y, o); break;
-      case 32: hipLaunchKernelGGL(lanczos_tile_kernel<32>, grid, block, 0, stream, x, y, o); break;
-      case 64: hipLaunchKernelGGL(lanczos_tile_kernel<64>, grid, block, 0, stream, x, y, o); break;
       case 128: hipLaunchKernelGGL(lanczos_tile_kernel<128>, grid, block, 0, stream, x, y, o); break;
       case 256:
         hipLaunchKernelGGL(lanczos_rows_kernel, grid, block, 0, stream, x, y, o);
