@@ -221,7 +221,7 @@ def main():
     achieved_tflops = float(flops_stamp.sum()) / (avg_kern_ms * 1e-3) / 1e12
     roofline = dict(bound="alu", achieved=round(achieved_tflops, 3), peak=round(FP32_FMA_NONPACKED_TFLOPS, 2),
                     unit="TFLOP/s", frac=round(achieved_tflops / FP32_FMA_NONPACKED_TFLOPS, 4), traffic=measured_traffic(),
-                    kernel="render_small_kernel<64, false>",
+                    kernel="render_small_kernel<64, false, false>",
                     flops_per_stamp=round(float(flops_stamp.mean()), 1),
                     algorithmic_bytes=args.n * (4 * W * W + 28),
                     hbm_gbps=round(args.n * (4 * W * W + 28) / (avg_kern_ms * 1e-3) / 1e9, 1))
