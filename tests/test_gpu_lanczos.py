@@ -58,6 +58,25 @@ def test_lanczos_each_size(ctx, W):
     psf.close(); mix.close()
 
 
+@pytest.mark.parametrize("W", [16, 32, 64, 128])
+def test_lanczos_edge_positions(ctx, W):
+    """Centres near and beyond the stamp's edges and corners, where the
+    integer part wraps the Fourier image (a cyclic roll) and the filter's
+    taps leave the stamp (zero weight): the fused store (W <= 64) and the
+    separate pass (W = 128) against the oracle."""
+    cfg = wl.config_metric(8)
+    base = cfg["gal"]
+    s = W / 64.0
+    xs = (np.array([0.3, 63.6, -2.4, 65.7, 0.9, 31.25, 62.1, 1.5]) * s).astype(np.float32)
+    ys = (np.array([0.6, 63.2, 1.1, -1.8, 63.9, 30.7, 0.2, 66.4]) * s).astype(np.float32)
+    gal = wl.Galaxies(xs, ys, base.flux, base.r_e, base.e1, base.e2, base.mix_id, np.full(8, W, np.int32))
+    psf, mix = lib_objects(ctx, cfg)
+    gpu = render_gpu(ctx, psf, mix, gal, W, flags=LZ)
+    idx = list(range(len(gal)))
+    _check(gpu, oracle_lanczos(cfg, gal, idx), idx)
+    psf.close(); mix.close()
+
+
 @pytest.mark.parametrize("extra", [1, 2])
 def test_lanczos_with_forced_routing(ctx, extra):
     rng = np.random.Generator(np.random.PCG64(950 + extra))
