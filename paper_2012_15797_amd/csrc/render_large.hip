@@ -28,29 +28,49 @@
 
 namespace gfc {
 
-namespace big {
-constexpr int W = 256;
-constexpr int D = 4;             // column-transform decimation
-constexpr int M = W / D;         // 64 values per item in the column phase
-constexpr int NC = W / 2;        // 128 regular columns
-constexpr int NL = NC * D;       // 512 (column, h) items: the column phase's order, and the PSF cache's
-constexpr int BLOCK = 256;       // threads per workgroup
-constexpr int NR = NL / BLOCK;   // rounds per phase
-constexpr int CCH = 32;          // columns per combine chunk
-constexpr int RCH = 64;          // rows per store chunk
-constexpr int RPL = 32;          // rows a thread finishes per pass over a store chunk
-constexpr int SLAB = (NC + 1) * W;  // float2 per stamp in the scratch slab
-// LDS: combine chunk = CCH*D*M float2 = 64 KB; store chunk = 2 halves x RCH x 64 float2 = 64 KB
-constexpr int LDS_F2 = CCH * D * M;
-static_assert(LDS_F2 == 2 * RCH * (W / 4), "shared buffer sizes differ");
-static_assert(NR == 2 && RCH == 2 * RPL, "two rounds per phase, two passes per store chunk");
-}  // namespace big
+template <int W_>
+struct LargeCfg {
+  static constexpr int W = W_;
+  static constexpr int D = 4;             // column-transform decimation
+  static constexpr int M = W / D;         // values per item in the column phase
+  static constexpr int NC = W / 2;        // regular columns
+  static constexpr int NL = NC * D;       // (column, h) items
+  static constexpr int BLOCK = 256;       // threads per workgroup
+  static constexpr int NR = NL / BLOCK;   // rounds per phase (1 at 128, 2 at 256)
+  static constexpr int CCH = 32;          // columns per combine chunk
+  static constexpr int RCH = 64;          // rows per store chunk
+  static constexpr int RPL = 32;          // rows a thread finishes per pass over a store chunk
+  static constexpr int XPT = BLOCK / W;   // threads per output column in the store (1 or 2)
+  static constexpr int PASSES = RCH / (RPL * XPT);
+  static constexpr int SLAB = (NC + 1) * W;  // float2 per stamp in the scratch slab
+  // LDS: combine chunk = CCH*D*M float2; store chunk = 2 halves x RCH x M float2
+  static constexpr int LDS_F2 = CCH * D * M;
+  static_assert(LDS_F2 == 2 * RCH * M, "shared buffer sizes differ");
+  static_assert(W == 128 || W == 256, "stamp sizes 128 and 256");
+  static_assert(XPT * W == BLOCK && NR * BLOCK == NL, "thread counts");
+  static_assert((NC / CCH) == 2 * NR && (W / RCH) == 2 * NR, "two combine and two store chunks per round");
+};
+
+// Index of bin (column c, row k_y) in the cached PSF spectrum: at 256 the
+// cache is in this kernel's item order (l = 4c + h, rows 4m + h); at 128 it is
+// in the order of the other 128 x 128 kernels (l = 2c + h', rows 2m' + h').
+template <int W>
+__device__ __forceinline__ int psf_index(int m, int l) {
+  if constexpr (W == 256) {
+    return m * (2 * W) + l;
+  } else {
+    const int c = l >> 2, h = l & 3;
+    return (2 * m + (h >> 1)) * W + 2 * c + (h & 1);
+  }
+}
 
 // EIG: spatially varying PSF (eigen-PSF components with polynomial weights).
-template <bool EIG>
-__global__ void __launch_bounds__(big::BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
-render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
-  using namespace big;
+template <int W, bool EIG>
+__global__ void __launch_bounds__(LargeCfg<W>::BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
+render_large_kernel(RenderArgs p, float2* __restrict__ scratch) {
+  using C = LargeCfg<W>;
+  constexpr int D = C::D, M = C::M, NC = C::NC, NL = C::NL, BLOCK = C::BLOCK, NR = C::NR, CCH = C::CCH,
+                RCH = C::RCH, RPL = C::RPL, SLAB = C::SLAB, LDS_F2 = C::LDS_F2;
   __shared__ float2 s_buf[LDS_F2];
   __shared__ float2 s_py[W + 2];
   __shared__ float2 s_nyq[W];
@@ -119,9 +139,10 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
       });
       qv[M] = fmaf(-0.5f, fmaf(g2, -0.5f, g1), g0);  // Nyquist row, omega = -1/2
 
-      // In round 0 thread t also takes row t of column k_x = 128: (+-1/2, omN).
-      // The corner's omega = -1/2 twins equal the (-+1/2, +1/2) pair of row
-      // W/2: the mixture transform is even.
+      // In round 0 thread t < W also takes row t of column k_x = W/2:
+      // (+-1/2, omN).  The corner's omega = -1/2 twins equal the (-+1/2, +1/2)
+      // pair of row W/2: the mixture transform is even.
+      const bool nyq = t < W;
       const float omN = (t < W / 2) ? (float)t * (1.f / W) : (t == W / 2 ? 0.5f : (float)(t - W) * (1.f / W));
       float qn[2];
       if constexpr (rd == 0) {
@@ -150,14 +171,16 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
           S[m] = fmaf(wa, __builtin_amdgcn_exp2f(v * qv[m]), S[m]);
         });
         if constexpr (rd == 0) {
-          static_for<0, 2>([&](auto jj) {
-            constexpr int j = decltype(jj)::value;
-            SN[j] = fmaf(wa, __builtin_amdgcn_exp2f(v * qn[j]), SN[j]);
-          });
+          if (nyq) {
+            static_for<0, 2>([&](auto jj) {
+              constexpr int j = decltype(jj)::value;
+              SN[j] = fmaf(wa, __builtin_amdgcn_exp2f(v * qn[j]), SN[j]);
+            });
+          }
         }
       }
 
-      if constexpr (rd == 0) {
+      if (rd == 0 && nyq) {
         // y phase of row t, the omega = -1/2 twin (conjugate of row W/2), and
         // the Nyquist column's row t
         float2 psfN;
@@ -183,8 +206,8 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
         const float2 plus = cadd(cscale(pyA, SN[0]), cscale(pyB, SN[1]));
         const float2 minus = cadd(cscale(pyA, SN[1]), cscale(pyB, SN[0]));
         s_nyq[t] = cmul(cscale(psfN, 0.5f * fs), cadd(cmul(eM, plus), cmul(eP, minus)));
-        __syncthreads();
       }
+      if constexpr (rd == 0) __syncthreads();
 
       float sx, cx;
       sincospi_poly(-2.f * G.fx * nu, &sx, &cx);
@@ -197,11 +220,11 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
           P = make_float2(0.f, 0.f);
           for (int j = 0; j < p.eig_J; ++j) {
             const float cj = s_cj[j];
-            const float2 q = p.psf_main[j * p.eig_stride + m * NL + l];
+            const float2 q = p.psf_main[j * p.eig_stride + psf_index<W>(m, l)];
             P = make_float2(fmaf(cj, q.x, P.x), fmaf(cj, q.y, P.y));
           }
         } else {
-          P = p.psf_main[m * NL + l];
+          P = p.psf_main[psf_index<W>(m, l)];
         }
         if constexpr (D * m == W / 2) {
           const float2 q0 = s_py[W / 2 + h];
@@ -212,7 +235,7 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
           Z[m] = cscale(cmul(cmul(P, s_py[D * m + h]), pxF), S[m]);
         }
       });
-      if (c == 0) {  // column 0 carries column 128 as its imaginary part
+      if (c == 0) {  // column 0 carries column W/2 as its imaginary part
         static_for<0, M>([&](auto mm) {
           constexpr int m = decltype(mm)::value;
           const float2 xn = s_nyq[D * m + h];
@@ -221,11 +244,11 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
       }
       fft<M, +1>(Z);
 
-      // Combine: X_c[j + 64 q] = sum_h i^{h q} w^{h j} E_{h,c}[j],
-      // w = exp(2 pi i / 256): one radix-4 butterfly per (column, j) gives the
-      // four rows j + 64 q.  Thread j of wavefront wv takes columns wv,
-      // wv + 4, ..., wv + 28 of the chunk.
-      const int j = t & (M - 1), wv = t >> 6;
+      // Combine: X_c[j + M q] = sum_h i^{h q} w^{h j} E_{h,c}[j],
+      // w = exp(2 pi i / W): one radix-4 butterfly per (column, j) gives the
+      // four rows j + M q.  Thread t takes j = t mod M and the chunk's
+      // columns t / M, t / M + BLOCK / M, ...
+      const int j = t & (M - 1), wv = t / M;
       const float2 w1 = twiddle_rt<+1, W>(j), w2 = twiddle_rt<+1, W>(2 * j), w3 = twiddle_rt<+1, W>(3 * j);
       static_for<0, 2>([&](auto tt) {
         constexpr int tc = 2 * rd + decltype(tt)::value;  // chunk: columns 32 tc .. 32 tc + 31
@@ -247,19 +270,19 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
           const int cg = tc * CCH + cl;
           if (cg == 0) {
             slab[j] = make_float2(x0.x, 0.f);
-            slab[j + 64] = make_float2(x1.x, 0.f);
-            slab[j + 128] = make_float2(x2.x, 0.f);
-            slab[j + 192] = make_float2(x3.x, 0.f);
+            slab[j + M] = make_float2(x1.x, 0.f);
+            slab[j + 2 * M] = make_float2(x2.x, 0.f);
+            slab[j + 3 * M] = make_float2(x3.x, 0.f);
             slab[NC * W + j] = make_float2(x0.y, 0.f);
-            slab[NC * W + j + 64] = make_float2(x1.y, 0.f);
-            slab[NC * W + j + 128] = make_float2(x2.y, 0.f);
-            slab[NC * W + j + 192] = make_float2(x3.y, 0.f);
+            slab[NC * W + j + M] = make_float2(x1.y, 0.f);
+            slab[NC * W + j + 2 * M] = make_float2(x2.y, 0.f);
+            slab[NC * W + j + 3 * M] = make_float2(x3.y, 0.f);
           } else {
             float2* o = slab + cg * W + j;
             o[0] = x0;
-            o[64] = x1;
-            o[128] = x2;
-            o[192] = x3;
+            o[M] = x1;
+            o[2 * M] = x2;
+            o[3 * M] = x3;
           }
         });
         __syncthreads();
@@ -268,9 +291,8 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
 
     // ------------------------------------------------------------ row phase + store
     // Round rr takes items l = t + 256 rr: wavefront wl = l / 64 takes rows
-    // 64 (wl / 2) .. +63 (rows 0..127, then 128..255) and the half q = wl % 2
-    // of the complex-to-real transform, R[k] for k = 2i + q; then the store
-    // chunks of those rows.
+    // 64 (wl / 2) .. +63 and the half q = wl % 2 of the complex-to-real
+    // transform, R[k] for k = 2i + q; then the store chunks of those rows.
     float* outp = p.out + stamp * (int64_t)(W * W);
     static_for<0, NR>([&](auto rrr) {
       constexpr int rr = decltype(rrr)::value;
@@ -282,7 +304,7 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
       const int y = ((wl >> 1) << 6) | (l & 63);
       float2 Rq[M];
       if (q == 0) {
-        // pairs (k, 128 - k) with k = 2i: indices i and 64 - i of X[2i]
+        // pairs (k, NC - k) with k = 2i: indices i and M - i of X[2i]
         float2 Xe[M + 1];
         static_for<0, M + 1>([&](auto ii) {
           constexpr int i = decltype(ii)::value;
@@ -298,7 +320,7 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
           if constexpr (i != 0 && 2 * i != M) Rq[M - i] = make_float2(sum.x + tt.y, tt.x - sum.y);
         });
       } else {
-        // pairs (k, 128 - k) with k = 2i + 1: indices i and 63 - i of X[2i + 1]
+        // pairs (k, NC - k) with k = 2i + 1: indices i and M - 1 - i of X[2i + 1]
         float2 Xo[M];
         static_for<0, M>([&](auto ii) {
           constexpr int i = decltype(ii)::value;
@@ -314,7 +336,7 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
           Rq[M - 1 - i] = make_float2(sum.x + tt.y, tt.x - sum.y);
         });
       }
-      fft<M, +1>(Rq);  // z_q[n] = sum_i R[2i + q] w64^{i n}
+      fft<M, +1>(Rq);  // z_q[n] = sum_i R[2i + q] w_M^{i n}
 
       static_for<0, 2>([&](auto tt) {
         constexpr int tc = 2 * rr + decltype(tt)::value;  // chunk: rows 64 tc .. 64 tc + 63
@@ -328,11 +350,13 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
         }
         __syncthreads();
         const float* tile = reinterpret_cast<const float*>(s_buf);
-        // z[n] = z_0[n mod 64] + s w128^{n mod 64} z_1[n mod 64], s = +1 (n < 64)
+        // z[n] = z_0[n mod M] + s w_{2M}^{n mod M} z_1[n mod M], s = +1 (n < M)
         // or -1; pixel x of the fractional image row is Re z[x/2] (x even) or
         // Im z[x/2]: value = z0.part + sg * (ca * z1.x + cb * z1.y)
-        int X = threadIdx.x;  // the output column this thread stores
-        asm volatile("" : "+v"(X));
+        int tx = threadIdx.x;
+        asm volatile("" : "+v"(tx));
+        const int X = tx & (W - 1);  // the output column this thread stores
+        const int rx = tx / W;       // and its share of the chunk's rows
         const int xs = (X - G.nx) & (W - 1);
         const int n = xs >> 1, nn = n & (M - 1);
         const float2 tw = twiddle_rt<+1, 2 * M>(nn);
@@ -341,17 +365,18 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
         const float ca = sg * (odd ? tw.y : tw.x);
         const float cb = sg * (odd ? tw.x : -tw.y);
         const float dx = (float)X - G.x0 - pg[0];
-        static_for<0, RCH / RPL>([&](auto hh) {
+        static_for<0, C::PASSES>([&](auto hh) {
           constexpr int rh = decltype(hh)::value;
+          const int srowb = (rh * C::XPT + rx) * RPL;  // first chunk row of this pass
           float val[RPL];
           static_for<0, RPL>([&](auto rq) {
             constexpr int r = decltype(rq)::value;
-            constexpr int srow = rh * RPL + r;
+            const int srow = srowb + r;
             const float z0 = tile[2 * (srow * M + nn) + (odd ? 1 : 0)];
             const float2 z1 = s_buf[(RCH + srow) * M + nn];
             val[r] = fmaf(ca, z1.x, fmaf(cb, z1.y, z0));
           });
-          const int srow0 = tc * RCH + rh * RPL;
+          const int srow0 = tc * RCH + srowb;
           for (unsigned mk = rmask; mk != 0; mk &= mk - 1) {
             const float2 rs = s_rs[__builtin_ctz(mk)];  // LDS, not global: no wait on the stores above
             const float v = rs.x, ra = rs.y;
@@ -387,15 +412,15 @@ render_w256_kernel(RenderArgs p, float2* __restrict__ scratch) {
 
 // Workgroups of one instantiation that stay resident at once (occupancy per
 // CU x CUs), queried once per instantiation.
-template <bool EIG>
-static hipError_t w256_resident(int64_t* out) {
+template <int W, bool EIG>
+static hipError_t large_resident(int64_t* out) {
   static int64_t cached = 0;
   if (cached == 0) {
     int dev = 0, cus = 0, per = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, render_w256_kernel<EIG>, big::BLOCK, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, render_large_kernel<W, EIG>, LargeCfg<W>::BLOCK, 0);
     if (e != hipSuccess) return e;
     cached = (int64_t)std::max(per, 1) * std::max(cus, 1);
   }
@@ -403,24 +428,25 @@ static hipError_t w256_resident(int64_t* out) {
   return hipSuccess;
 }
 
-hipError_t launch_render_w256(const RenderArgs& args, hipStream_t stream) {
-  using namespace big;
-  // As many workgroups as stay resident (two per CU), each with its own slab
-  // of 264 KB.
+template <int W, bool EIG>
+static hipError_t launch_large(const RenderArgs& args, hipStream_t stream) {
+  using C = LargeCfg<W>;
+  // As many workgroups as stay resident, each with its own slab.
   int64_t resident = 0;
-  hipError_t e = args.eig_J > 0 ? w256_resident<true>(&resident) : w256_resident<false>(&resident);
+  hipError_t e = large_resident<W, EIG>(&resident);
   if (e != hipSuccess) return e;
   const int64_t nb = std::min<int64_t>(args.n, resident);
   float2* scratch = nullptr;
-  e = hipMallocAsync((void**)&scratch, (size_t)nb * SLAB * sizeof(float2), stream);
+  e = hipMallocAsync((void**)&scratch, (size_t)nb * C::SLAB * sizeof(float2), stream);
   if (e != hipSuccess) return e;
-  if (args.eig_J > 0)
-    hipLaunchKernelGGL(render_w256_kernel<true>, dim3((unsigned)nb), dim3(BLOCK), 0, stream, args, scratch);
-  else
-    hipLaunchKernelGGL(render_w256_kernel<false>, dim3((unsigned)nb), dim3(BLOCK), 0, stream, args, scratch);
+  hipLaunchKernelGGL((render_large_kernel<W, EIG>), dim3((unsigned)nb), dim3(C::BLOCK), 0, stream, args, scratch);
   e = hipGetLastError();
   hipError_t e2 = hipFreeAsync(scratch, stream);
   return e != hipSuccess ? e : e2;
+}
+
+hipError_t launch_render_w256(const RenderArgs& args, hipStream_t stream) {
+  return args.eig_J > 0 ? launch_large<256, true>(args, stream) : launch_large<256, false>(args, stream);
 }
 
 }  // namespace gfc
