@@ -145,6 +145,32 @@ def test_accumulate_two_shapes_in_one_stamp(ctx):
     psf.close(); mix.close()
 
 
+@pytest.mark.parametrize("W", [16, 128, 256])
+def test_accumulate_each_size(ctx, W):
+    """GFC_ACCUMULATE at the other stamp sizes (several stamps per wavefront,
+    two wavefronts per stamp, the persistent 256 x 256 kernel): a second render
+    into the same stamps adds to them."""
+    import paper_2012_15797_amd as gfc
+    cfg = wl.config_composite(10)
+    rng = np.random.Generator(np.random.PCG64(1050 + W))
+    n = 12 if W < 256 else 4
+    disk = wl.draw_galaxies(rng, n, W, 0, r_e_range=(0.5, W / 8.0))
+    bulge = wl.draw_galaxies(rng, n, W, 1, r_e_range=(0.3, W / 16.0))
+    psf = gfc.Psf(ctx, cfg["psf"])
+    mix = gfc.Mixture.from_workload(ctx, cfg["mix"].as_f32())
+    out = gfc.gfc_render_stamps(ctx, psf, mix, disk.x, disk.y, disk.flux, disk.r_e, disk.e1, disk.e2, W,
+                                mix_id=disk.mix_id)
+    gfc.gfc_render_stamps(ctx, psf, mix, bulge.x, bulge.y, bulge.flux, bulge.r_e, bulge.e1, bulge.e2, W,
+                          mix_id=bulge.mix_id, flags=gfc.GFC_ACCUMULATE, out=out)
+    gpu = _np(out)
+    P = cfg["psf"].astype(np.float64)
+    idx = list(range(n))
+    ref_d = o.render_batch(P, cfg["mix"].as_f32(), disk, idx=idx)
+    ref_b = o.render_batch(P, cfg["mix"].as_f32(), bulge, idx=idx)
+    _check(gpu, [a + b for a, b in zip(ref_d, ref_b)], idx)
+    psf.close(); mix.close()
+
+
 def test_profile_errors(ctx):
     import paper_2012_15797_amd as gfc
     cfg = wl.config_composite(4)
