@@ -40,6 +40,10 @@ GFC_HD float2 cmul(float2 a, float2 b) {
 GFC_HD float2 cmulc(float2 a, float2 b) {
   return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -(a.x * b.y)));
 }
+// a b + c in four FMAs
+GFC_HD float2 cfma(float2 a, float2 b, float2 c) {
+  return make_float2(fmaf(a.x, b.x, fmaf(-a.y, b.y, c.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, c.y)));
+}
 // multiply by SIGN * i
 template <int SIGN>
 GFC_HD float2 rot90(float2 v) {
@@ -68,58 +72,130 @@ GFC_HD float2 twiddle(float2 v) {
   }
 }
 
-// Radix of the decimation-in-frequency stage working on blocks of length L:
-// radix 2 when log2(L) is odd (only the first stage), radix 4 otherwise.
-constexpr int dif_radix(int L) { return (ilog2(L) & 1) ? 2 : 4; }
+// A twiddle w = exp(SIGN 2 pi i K / L) as a real scale r times a factor
+// applied by unit(v), so that w v = r unit(v).  For 1, -1 and +-i, r = 1 and
+// unit is the exact product.  Otherwise w = r (1 + i q) when |cos| >= |sin|,
+// else r (q + i), with |q| <= 1 (the tangent or cotangent), and unit takes
+// two FMAs: a product w v that feeds an add then folds into FMAs.
+template <int SIGN, int L, int K>
+struct TwFactor {
+  static constexpr int k = ((K % L) + L) % L;
+  static constexpr bool trivial = (4 * k) % L == 0;
+  static constexpr int t = trivial ? 0 : k * (GFC_TW_N / L);
+  static constexpr float c = kTwCos[t];
+  static constexpr float s = SIGN > 0 ? kTwSin[t] : -kTwSin[t];
+  static constexpr bool by_cos = (c >= 0.f ? c : -c) >= (s >= 0.f ? s : -s);
+  static constexpr float r = trivial ? 1.f : (by_cos ? c : s);
+  static constexpr float q = SIGN > 0 ? kTwRatio[t] : -kTwRatio[t];
+  static GFC_HD float2 unit(float2 v) {
+    if constexpr (trivial) return twiddle<SIGN, L, K>(v);
+    else if constexpr (by_cos) return make_float2(fmaf(-q, v.y, v.x), fmaf(q, v.x, v.y));
+    else return make_float2(fmaf(q, v.x, -v.y), fmaf(q, v.y, v.x));
+  }
+};
 
-// Position of output k after the DIF stages of a length-L transform.
-constexpr int dif_pos(int L, int k) {
-  return L == 1 ? 0 : (k % dif_radix(L)) * (L / dif_radix(L)) + dif_pos(L / dif_radix(L), k / dif_radix(L));
+// Radix-2 butterfly (a, b) <- (a + w b, a - w b), w = exp(SIGN 2 pi i K / L):
+// four adds when w is 1, -1 or +-i, otherwise six FMAs (w b = r u with
+// u = unit(b), then a +- r u), against four adds and a complex product.
+template <int SIGN, int L, int K>
+GFC_HD void bfly2(float2& a, float2& b) {
+  constexpr int k = ((K % L) + L) % L;
+  const float2 p = a;
+  if constexpr (k == 0) {
+    a = cadd(p, b);
+    b = csub(p, b);
+  } else if constexpr (2 * k == L) {
+    a = csub(p, b);
+    b = cadd(p, b);
+  } else if constexpr (4 * k == L || 4 * k == 3 * L) {
+    const float2 wb = (4 * k == L) ? rot90<SIGN>(b) : rot90<-SIGN>(b);
+    a = cadd(p, wb);
+    b = csub(p, wb);
+  } else {
+    static_assert(GFC_TW_N % L == 0, "twiddle table too small");
+    using T = TwFactor<SIGN, L, k>;
+    static_assert(!T::trivial, "trivial twiddles take the branches above");
+    const float2 u = T::unit(b);
+    a = make_float2(fmaf(T::r, u.x, p.x), fmaf(T::r, u.y, p.y));
+    b = make_float2(fmaf(-T::r, u.x, p.x), fmaf(-T::r, u.y, p.y));
+  }
 }
 
+// Pair step of a complex-to-real inverse transform run as a half-length
+// complex FFT: with s = a + b, t = w (a - b), w = exp(SIGN 2 pi i K / L),
+// lo = s + i t and hi = conj(s) + i conj(t).  t = r u (TwFactor), so each
+// output component is one FMA.
+template <int SIGN, int L, int K>
+GFC_HD void c2r_pair(float2 a, float2 b, float2& lo, float2& hi) {
+  using T = TwFactor<SIGN, L, K>;
+  const float2 sum = cadd(a, b);
+  const float2 u = T::unit(csub(a, b));
+  lo = make_float2(fmaf(-T::r, u.y, sum.x), fmaf(T::r, u.x, sum.y));
+  hi = make_float2(fmaf(T::r, u.y, sum.x), fmaf(T::r, u.x, -sum.y));
+}
+
+// Radix of the stage combining sub-transforms into blocks of length L:
+// radix 2 when log2(L) is odd (only the last stage), radix 4 otherwise.
+constexpr int stage_radix(int L) { return (ilog2(L) & 1) ? 2 : 4; }
+
+// Register holding input n of a length-L transform before the stages run
+// (mixed-radix digit reversal): block p of length L/R holds the
+// sub-sequence n = p (mod R), recursively.
+constexpr int in_pos(int L, int n) {
+  return L == 1 ? 0 : (n % stage_radix(L)) * (L / stage_radix(L)) + in_pos(L / stage_radix(L), n / stage_radix(L));
+}
+
+// Decimation-in-time stages up to block length L: the blocks of length L/R
+// hold the R sub-transforms, and butterfly j of a block forms outputs
+// j + (L/R) q from element j of each.  The twiddles meet the inputs of the
+// butterflies, where they fold into FMAs (bfly2).  Radix 4 as four radix-2
+// butterflies: with w = exp(SIGN 2 pi i / L) and sub-transforms X0..X3,
+//   t0, t1 = X0 +- w^2j X2;  p, q = X1 +- w^2j X3;
+//   y0, y2 = t0 +- w^j p;    y1, y3 = t1 +- w^(j + L/4) q,
+// where w^(L/4) = SIGN i.
 template <int N, int SIGN, int L>
-GFC_HD void dif_stage(float2 (&a)[N]) {
+GFC_HD void dit_stages(float2 (&a)[N]) {
   if constexpr (L >= 2) {
-    constexpr int R = dif_radix(L);
+    constexpr int R = stage_radix(L);
+    dit_stages<N, SIGN, L / R>(a);
     static_for<0, N / L>([&](auto sb) {
       static_for<0, L / R>([&](auto jj) {
         constexpr int j = decltype(jj)::value;
         constexpr int base = decltype(sb)::value * L + j;
         if constexpr (R == 2) {
-          constexpr int H = L / 2;
-          const float2 x0 = a[base], x1 = a[base + H];
-          a[base] = cadd(x0, x1);
-          a[base + H] = twiddle<SIGN, L, j>(csub(x0, x1));
+          bfly2<SIGN, L, j>(a[base], a[base + L / 2]);
         } else {
           constexpr int Q = L / 4;
-          const float2 x0 = a[base], x1 = a[base + Q], x2 = a[base + 2 * Q], x3 = a[base + 3 * Q];
-          const float2 t0 = cadd(x0, x2), t1 = csub(x0, x2);
-          const float2 t2 = cadd(x1, x3), t3 = rot90<SIGN>(csub(x1, x3));
-          a[base] = cadd(t0, t2);
-          a[base + Q] = twiddle<SIGN, L, j>(cadd(t1, t3));
-          a[base + 2 * Q] = twiddle<SIGN, L, 2 * j>(csub(t0, t2));
-          a[base + 3 * Q] = twiddle<SIGN, L, 3 * j>(csub(t1, t3));
+          float2 x0 = a[base], x1 = a[base + Q], x2 = a[base + 2 * Q], x3 = a[base + 3 * Q];
+          bfly2<SIGN, L, 2 * j>(x0, x2);
+          bfly2<SIGN, L, 2 * j>(x1, x3);
+          bfly2<SIGN, L, j>(x0, x1);
+          bfly2<SIGN, L, j + Q>(x2, x3);
+          a[base] = x0;
+          a[base + Q] = x2;
+          a[base + 2 * Q] = x1;
+          a[base + 3 * Q] = x3;
         }
       });
     });
-    dif_stage<N, SIGN, L / R>(a);
   }
 }
 
 // In-place unnormalised DFT of length N (power of two, 1..256):
-//   a[k] <- sum_n a[n] exp(SIGN * 2 pi i k n / N),  natural order in and out.
+//   a[k] <- sum_n a[n] exp(SIGN 2 pi i k n / N),  natural order in and out.
+// The input permutation is a renaming of registers and costs nothing.
 template <int N, int SIGN>
 GFC_HD void fft(float2 (&a)[N]) {
-  dif_stage<N, SIGN, N>(a);
   float2 t[N];
-  static_for<0, N>([&](auto kk) {
-    constexpr int k = decltype(kk)::value;
-    t[k] = a[dif_pos(N, k)];
+  static_for<0, N>([&](auto nn) {
+    constexpr int n = decltype(nn)::value;
+    t[in_pos(N, n)] = a[n];
   });
-  static_for<0, N>([&](auto kk) {
-    constexpr int k = decltype(kk)::value;
-    a[k] = t[k];
+  static_for<0, N>([&](auto nn) {
+    constexpr int n = decltype(nn)::value;
+    a[n] = t[n];
   });
+  dit_stages<N, SIGN, N>(a);
 }
 
 // Runtime twiddle exp(SIGN * 2 pi i k / L) for a lane-dependent k (table lookup).

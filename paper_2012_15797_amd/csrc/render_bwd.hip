@@ -186,9 +186,11 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
       const float2 a = Zr[k], b = cconj(Zr[kc]);
       const float2 e2 = cadd(a, b);
       const float2 o2 = rot90<-1>(csub(a, b));      // -i (a - b)
-      const float2 t2 = twiddle<-1, W, k>(o2);
-      gr[y * (M + 1) + k] = cadd(e2, t2);
-      if constexpr (2 * k != M) gr[y * (M + 1) + (M - k)] = cconj(csub(e2, t2));
+      // t2 = exp(-2 pi i k / W) o2 = r u (TwFactor): e2 +- t2 as FMAs
+      using T = TwFactor<-1, W, k>;
+      const float2 u = T::unit(o2);
+      gr[y * (M + 1) + k] = make_float2(fmaf(T::r, u.x, e2.x), fmaf(T::r, u.y, e2.y));
+      if constexpr (2 * k != M) gr[y * (M + 1) + (M - k)] = make_float2(fmaf(-T::r, u.x, e2.x), fmaf(T::r, u.y, -e2.y));
     });
   }
   __syncthreads();

@@ -333,7 +333,7 @@ render_small_kernel(RenderArgs p) {
       constexpr int cI = pass * QC + cl;
       const float2 e0 = s_t1[slot][jr * T1S + 2 * cl];
       const float2 e1 = s_t1[slot][jr * T1S + 2 * cl + 1];
-      const float2 v = cadd(e0, cmul(tw, e1));
+      const float2 v = cfma(tw, e1, e0);
       if constexpr (cI == 0) {
         X[0] = make_float2(v.x, 0.f);
         X[NC] = make_float2(v.y, 0.f);
@@ -349,11 +349,10 @@ render_small_kernel(RenderArgs p) {
   float2 R[NC];
   static_for<0, NC / 2 + 1>([&](auto kk) {
     constexpr int k = decltype(kk)::value;
-    const float2 a = X[k], b = cconj(X[NC - k]);
-    const float2 sum = cadd(a, b);
-    const float2 t = twiddle<+1, W, k>(csub(a, b));
-    R[k] = make_float2(sum.x - t.y, sum.y + t.x);
-    if constexpr (k != 0 && 2 * k != NC) R[NC - k] = make_float2(sum.x + t.y, t.x - sum.y);
+    float2 lo, hi;
+    c2r_pair<+1, W, k>(X[k], cconj(X[NC - k]), lo, hi);
+    R[k] = lo;
+    if constexpr (k != 0 && 2 * k != NC) R[NC - k] = hi;
   });
   fft<NC, +1>(R);
 

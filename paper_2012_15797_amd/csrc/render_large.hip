@@ -313,11 +313,10 @@ render_large_kernel(RenderArgs p, float2* __restrict__ scratch) {
         static_for<0, M / 2 + 1>([&](auto ii) {
           constexpr int i = decltype(ii)::value;
           constexpr int k = 2 * i;
-          const float2 a = Xe[i], b = cconj(Xe[M - i]);
-          const float2 sum = cadd(a, b);
-          const float2 tt = twiddle<+1, W, k>(csub(a, b));
-          Rq[i] = make_float2(sum.x - tt.y, sum.y + tt.x);
-          if constexpr (i != 0 && 2 * i != M) Rq[M - i] = make_float2(sum.x + tt.y, tt.x - sum.y);
+          float2 lo, hi;
+          c2r_pair<+1, W, k>(Xe[i], cconj(Xe[M - i]), lo, hi);
+          Rq[i] = lo;
+          if constexpr (i != 0 && 2 * i != M) Rq[M - i] = hi;
         });
       } else {
         // pairs (k, NC - k) with k = 2i + 1: indices i and M - 1 - i of X[2i + 1]
@@ -329,11 +328,7 @@ render_large_kernel(RenderArgs p, float2* __restrict__ scratch) {
         static_for<0, M / 2>([&](auto ii) {
           constexpr int i = decltype(ii)::value;
           constexpr int k = 2 * i + 1;
-          const float2 a = Xo[i], b = cconj(Xo[M - 1 - i]);
-          const float2 sum = cadd(a, b);
-          const float2 tt = twiddle<+1, W, k>(csub(a, b));
-          Rq[i] = make_float2(sum.x - tt.y, sum.y + tt.x);
-          Rq[M - 1 - i] = make_float2(sum.x + tt.y, tt.x - sum.y);
+          c2r_pair<+1, W, k>(Xo[i], cconj(Xo[M - 1 - i]), Rq[i], Rq[M - 1 - i]);
         });
       }
       fft<M, +1>(Rq);  // z_q[n] = sum_i R[2i + q] w_M^{i n}
