@@ -207,6 +207,11 @@ __device__ __forceinline__ float stamp_lane1(float v) {
   }
 }
 
+// Value of v in lane k of the wavefront (k uniform).
+__device__ __forceinline__ float lane_f(float v, int k) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), k));
+}
+
 // Raw Lanczos-3 value at t (exact zeros at the integers other than 0), for
 // the optional pixel-space sub-pixel shift (Section 2, step 8).
 __device__ __forceinline__ float lanczos3(float t) {

@@ -109,14 +109,24 @@ render_small_kernel(RenderArgs p) {
   const float g0 = kQ * G.b11 * nu * nu;
   const float g1 = 2.f * kQ * G.b12 * nu;
   const float g2 = kQ * G.b22;
+  // Row k_y = 2m + h has omega = c_m + h/W with a compile-time c_m, so the
+  // quadratic is expanded about h/W: q = e0 + c_m (e1 + c_m g2), two FMAs
+  // with an immediate c_m per bin (e0 = q(h/W), e1 = q'(h/W); for h = 0 they
+  // are g0 and g1 and the result is the plain quadratic in omega).
+  const float e0 = fmaf(hW, fmaf(g2, hW, g1), g0);
+  const float e1 = fmaf(2.f * g2, hW, g1);
   float qv[M + 1];
   static_for<0, M>([&](auto mm) {
     constexpr int m = decltype(mm)::value;
-    float om;
-    if constexpr (2 * m < W / 2) om = (float)(2 * m) * (1.f / W) + hW;
-    else if constexpr (2 * m == W / 2) om = h ? (float)(W / 2 + 1 - W) * (1.f / W) : 0.5f;
-    else om = (float)(2 * m - W) * (1.f / W) + hW;
-    qv[m] = fmaf(om, fmaf(g2, om, g1), g0);
+    if constexpr (2 * m == W / 2) {
+      const float om = h ? (float)(W / 2 + 1 - W) * (1.f / W) : 0.5f;
+      qv[m] = fmaf(om, fmaf(g2, om, g1), g0);
+    } else if constexpr (m == 0) {
+      qv[m] = e0;
+    } else {
+      constexpr float cm = (2 * m < W / 2) ? (float)(2 * m) * (1.f / W) : (float)(2 * m - W) * (1.f / W);
+      qv[m] = fmaf(cm, fmaf(cm, g2, e1), e0);
+    }
   });
   qv[M] = fmaf(-0.5f, fmaf(g2, -0.5f, g1), g0);  // Nyquist row, omega = -1/2
 
@@ -135,15 +145,7 @@ render_small_kernel(RenderArgs p) {
   float S[M + 1];
   float SN[2];
   unsigned rmask = 0;  // components with a real-space share
-  {
-    const float v = var[0];
-    const float A = amp[0];
-    const float w = route_weight<W>(v * trB, p.flags);
-    if (w < 1.f && A != 0.f) {
-      rmask = 1u;
-      if (l == 0) s_rs[slot][0] = make_float2(v, (1.f - w) * A);
-    }
-    const float wa = w * A;
+  auto first_terms = [&](float v, float wa) {
     static_for<0, M + 1>([&](auto mm) {
       constexpr int m = decltype(mm)::value;
       S[m] = wa * __builtin_amdgcn_exp2f(v * qv[m]);
@@ -152,17 +154,8 @@ render_small_kernel(RenderArgs p) {
       constexpr int j = decltype(jj)::value;
       SN[j] = wa * __builtin_amdgcn_exp2f(v * qn[j]);
     });
-  }
-  for (int k = 1; k < kloop; ++k) {
-    const float v = var[k];
-    const float A = (k < G.K) ? amp[k] : 0.f;
-    const float w = route_weight<W>(v * trB, p.flags);
-    if (w < 1.f && A != 0.f) {
-      rmask |= 1u << k;
-      if (l == 0) s_rs[slot][k] = make_float2(v, (1.f - w) * A);
-    }
-    const float wa = w * A;
-    if (wa == 0.f) continue;
+  };
+  auto add_terms = [&](float v, float wa) {
     static_for<0, M + 1>([&](auto mm) {
       constexpr int m = decltype(mm)::value;
       S[m] = fmaf(wa, __builtin_amdgcn_exp2f(v * qv[m]), S[m]);
@@ -171,6 +164,51 @@ render_small_kernel(RenderArgs p) {
       constexpr int j = decltype(jj)::value;
       SN[j] = fmaf(wa, __builtin_amdgcn_exp2f(v * qn[j]), SN[j]);
     });
+  };
+  if constexpr (C::WAVE1) {
+    // One stamp per wavefront: lane k works out the route weight of component
+    // k once (K <= 16 lanes), and the loop takes v and w A from lane k.
+    const int lk = (int)__lane_id();
+    float vk = 0.f, wak = 0.f;
+    bool rk = false;
+    if (lk < G.K) {
+      vk = var[lk];
+      const float Ak = amp[lk];
+      const float wk = route_weight<W>(vk * trB, p.flags);
+      wak = wk * Ak;
+      rk = wk < 1.f && Ak != 0.f;
+      if (rk && l == lk) s_rs[slot][lk] = make_float2(vk, (1.f - wk) * Ak);
+    }
+    rmask = (unsigned)__ballot(rk);
+    first_terms(lane_f(vk, 0), lane_f(wak, 0));
+    for (int k = 1; k < G.K; ++k) {
+      const float wa = lane_f(wak, k);
+      if ((__builtin_bit_cast(unsigned, wa) << 1) == 0u) continue;  // w A = +-0
+      add_terms(lane_f(vk, k), wa);
+    }
+  } else {
+    {
+      const float v = var[0];
+      const float A = amp[0];
+      const float w = route_weight<W>(v * trB, p.flags);
+      if (w < 1.f && A != 0.f) {
+        rmask = 1u;
+        if (l == 0) s_rs[slot][0] = make_float2(v, (1.f - w) * A);
+      }
+      first_terms(v, w * A);
+    }
+    for (int k = 1; k < kloop; ++k) {
+      const float v = var[k];
+      const float A = (k < G.K) ? amp[k] : 0.f;
+      const float w = route_weight<W>(v * trB, p.flags);
+      if (w < 1.f && A != 0.f) {
+        rmask |= 1u << k;
+        if (l == 0) s_rs[slot][k] = make_float2(v, (1.f - w) * A);
+      }
+      const float wa = w * A;
+      if (wa == 0.f) continue;
+      add_terms(v, wa);
+    }
   }
 
   // PSF spectrum of this lane's bins and the PSF Gaussian (step 2; for a

@@ -128,14 +128,22 @@ render_large_kernel(RenderArgs p, float2* __restrict__ scratch) {
       const float g0 = kQ * G.b11 * nu * nu;
       const float g1 = 2.f * kQ * G.b12 * nu;
       const float g2 = kQ * G.b22;
+      // omega = c_m + h/W with a compile-time c_m: the quadratic expanded
+      // about h/W is two FMAs with an immediate per bin
+      const float e0 = fmaf(hW, fmaf(g2, hW, g1), g0);
+      const float e1 = fmaf(2.f * g2, hW, g1);
       float qv[M + 1];
       static_for<0, M>([&](auto mm) {
         constexpr int m = decltype(mm)::value;
-        float om;
-        if constexpr (D * m < W / 2) om = (float)(D * m) * (1.f / W) + hW;
-        else if constexpr (D * m == W / 2) om = h ? (float)(W / 2 - W) * (1.f / W) + hW : 0.5f;
-        else om = (float)(D * m - W) * (1.f / W) + hW;
-        qv[m] = fmaf(om, fmaf(g2, om, g1), g0);
+        if constexpr (D * m == W / 2) {
+          const float om = h ? (float)(W / 2 - W) * (1.f / W) + hW : 0.5f;
+          qv[m] = fmaf(om, fmaf(g2, om, g1), g0);
+        } else if constexpr (m == 0) {
+          qv[m] = e0;
+        } else {
+          constexpr float cm = (D * m < W / 2) ? (float)(D * m) * (1.f / W) : (float)(D * m - W) * (1.f / W);
+          qv[m] = fmaf(cm, fmaf(cm, g2, e1), e0);
+        }
       });
       qv[M] = fmaf(-0.5f, fmaf(g2, -0.5f, g1), g0);  // Nyquist row, omega = -1/2
 
