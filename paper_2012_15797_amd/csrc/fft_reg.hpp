@@ -134,9 +134,10 @@ GFC_HD void c2r_pair(float2 a, float2 b, float2& lo, float2& hi) {
   hi = make_float2(fmaf(T::r, u.y, sum.x), fmaf(T::r, u.x, -sum.y));
 }
 
-// Radix of the stage combining sub-transforms into blocks of length L:
-// radix 2 when log2(L) is odd (only the last stage), radix 4 otherwise.
-constexpr int stage_radix(int L) { return (ilog2(L) & 1) ? 2 : 4; }
+// Radix of the stage combining sub-transforms into blocks of length L: 2 for
+// the first stage of an odd power of two (L = 2), 4 otherwise, so the
+// largest blocks, where most twiddles are non-trivial, are radix 4.
+constexpr int stage_radix(int L) { return L == 2 ? 2 : 4; }
 
 // Register holding input n of a length-L transform before the stages run
 // (mixed-radix digit reversal): block p of length L/R holds the
@@ -145,14 +146,46 @@ constexpr int in_pos(int L, int n) {
   return L == 1 ? 0 : (n % stage_radix(L)) * (L / stage_radix(L)) + in_pos(L / stage_radix(L), n / stage_radix(L));
 }
 
+// Radix-4 butterfly j of a block of length L on element j of the four
+// sub-transforms X0..X3, w = exp(SIGN 2 pi i / L), w^(L/4) = SIGN i:
+//   t0, t1 = X0 +- w^2j X2;   b1 +- b3 = w^j X1 +- w^3j X3;
+//   y0, y2 = t0 +- (b1 + b3); y1, y3 = t1 +- SIGN i (b1 - b3).
+// With w^j = r1 unit1, w^3j = r3 unit3 (TwFactor), b1 +- b3 = r1 (u1 +- (r3/r1) u3),
+// so every product folds into an FMA: 22 instructions when all three
+// twiddles are non-trivial, against 24 for four radix-2 butterflies.
+template <int SIGN, int L, int J>
+GFC_HD void bfly4(float2& x0, float2& x1, float2& x2, float2& x3) {
+  using T1 = TwFactor<SIGN, L, J>;
+  using T3 = TwFactor<SIGN, L, 3 * J>;
+  if constexpr (T1::trivial || T3::trivial) {
+    // j = 0 (all trivial): the plain radix-4 butterfly
+    bfly2<SIGN, L, 2 * J>(x0, x2);
+    bfly2<SIGN, L, 2 * J>(x1, x3);
+    bfly2<SIGN, L, J>(x0, x1);
+    bfly2<SIGN, L, J + L / 4>(x2, x3);
+    const float2 t = x1;
+    x1 = x2;
+    x2 = t;
+  } else {
+    bfly2<SIGN, L, 2 * J>(x0, x2);  // x0 = t0, x2 = t1
+    constexpr float rho = T3::r / T1::r;
+    const float2 u1 = T1::unit(x1), u3 = T3::unit(x3);
+    const float2 sp = make_float2(fmaf(rho, u3.x, u1.x), fmaf(rho, u3.y, u1.y));
+    const float2 dp = make_float2(fmaf(-rho, u3.x, u1.x), fmaf(-rho, u3.y, u1.y));
+    constexpr float r = T1::r;
+    constexpr float ri = SIGN > 0 ? T1::r : -T1::r;  // SIGN i r1 dp = (-ri dp.y, ri dp.x)
+    const float2 t0 = x0, t1 = x2;
+    x0 = make_float2(fmaf(r, sp.x, t0.x), fmaf(r, sp.y, t0.y));
+    x2 = make_float2(fmaf(-r, sp.x, t0.x), fmaf(-r, sp.y, t0.y));
+    x1 = make_float2(fmaf(-ri, dp.y, t1.x), fmaf(ri, dp.x, t1.y));
+    x3 = make_float2(fmaf(ri, dp.y, t1.x), fmaf(-ri, dp.x, t1.y));
+  }
+}
+
 // Decimation-in-time stages up to block length L: the blocks of length L/R
 // hold the R sub-transforms, and butterfly j of a block forms outputs
 // j + (L/R) q from element j of each.  The twiddles meet the inputs of the
-// butterflies, where they fold into FMAs (bfly2).  Radix 4 as four radix-2
-// butterflies: with w = exp(SIGN 2 pi i / L) and sub-transforms X0..X3,
-//   t0, t1 = X0 +- w^2j X2;  p, q = X1 +- w^2j X3;
-//   y0, y2 = t0 +- w^j p;    y1, y3 = t1 +- w^(j + L/4) q,
-// where w^(L/4) = SIGN i.
+// butterflies, where they fold into FMAs (bfly2, bfly4).
 template <int N, int SIGN, int L>
 GFC_HD void dit_stages(float2 (&a)[N]) {
   if constexpr (L >= 2) {
@@ -166,15 +199,7 @@ GFC_HD void dit_stages(float2 (&a)[N]) {
           bfly2<SIGN, L, j>(a[base], a[base + L / 2]);
         } else {
           constexpr int Q = L / 4;
-          float2 x0 = a[base], x1 = a[base + Q], x2 = a[base + 2 * Q], x3 = a[base + 3 * Q];
-          bfly2<SIGN, L, 2 * j>(x0, x2);
-          bfly2<SIGN, L, 2 * j>(x1, x3);
-          bfly2<SIGN, L, j>(x0, x1);
-          bfly2<SIGN, L, j + Q>(x2, x3);
-          a[base] = x0;
-          a[base + Q] = x2;
-          a[base + 2 * Q] = x1;
-          a[base + 3 * Q] = x3;
+          bfly4<SIGN, L, j>(a[base], a[base + Q], a[base + 2 * Q], a[base + 3 * Q]);
         }
       });
     });

@@ -535,10 +535,16 @@ render_small_kernel(RenderArgs p) {
           const float a2 = kHalfLog2e * (sxx * rdet);
           const float dyb = (float)ybase + dyc;
           const float dybw = dyb - (float)W;
-          static_for<0, C::HR>([&](auto rr) {
-            constexpr int r = decltype(rr)::value;
-            const float dy = ((r >= rwrap) ? dybw : dyb) + (float)r;
-            val[r] = fmaf(ampr, __builtin_amdgcn_exp2f(fmaf(dy, fmaf(a2, dy, a1), a0)), val[r]);
+          // two rows at a time, so that each exponential has an independent
+          // instruction between it and its use
+          static_for<0, C::HR / 2>([&](auto rr) {
+            constexpr int r = 2 * decltype(rr)::value;
+            const float dy0 = ((r >= rwrap) ? dybw : dyb) + (float)r;
+            const float dy1 = ((r + 1 >= rwrap) ? dybw : dyb) + (float)(r + 1);
+            const float g0 = __builtin_amdgcn_exp2f(fmaf(dy0, fmaf(a2, dy0, a1), a0));
+            const float g1 = __builtin_amdgcn_exp2f(fmaf(dy1, fmaf(a2, dy1, a1), a0));
+            val[r] = fmaf(ampr, g0, val[r]);
+            val[r + 1] = fmaf(ampr, g1, val[r + 1]);
           });
         }
       }
