@@ -126,29 +126,34 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
         const float syy = fmaf(v, G.b22, p.pg[4]);
         const float det = fmaf(sxx, syy, -(sxy * sxy));
         const float rdet = __builtin_amdgcn_rcpf(det);
-        const float ixx = syy * rdet, ixy = -sxy * rdet, iyy = sxx * rdet;
+        const float ixy = -sxy * rdet, iyy = sxx * rdet;
         const float nrm = kInv2Pi * __builtin_amdgcn_rsqf(det);
-        float a0 = 0.f, ax = 0.f, ay = 0.f, axx = 0.f, axy = 0.f, ayy = 0.f;
         const float dy0 = (float)r0 - G.y0 - p.pg[1];
-        // per lane: z = S^-1 (dx, dy) = (cx + ixy dy, cy + iyy dy), and the log2 of
-        // nrm exp(-q/2) as e0 + dy (e1 + e2 dy), the normalisation folded in
-        const float cx = ixx * dx, cy = ixy * dx;
-        const float e0 = fmaf(kHalfLog2e * ixx, dx * dx, __builtin_amdgcn_logf(nrm));
-        const float e1 = 2.f * kHalfLog2e * cy, e2 = kHalfLog2e * iyy;
+        // Along this lane's column, z = S^-1 (dx, dy) has zy = ixy dx + iyy dy
+        // and zx = al + be zy with al = dx / sxx, be = -sxy / sxx, and the
+        // quadratic form is q = dx al + zy^2 / iyy.  So the column needs the
+        // moments sum g N zy^p (p = 0, 1, 2) only, with the log2 of
+        // nrm exp(-q/2) as c0 + c2 zy^2 (the normalisation folded in).
+        const float rsxx = __builtin_amdgcn_rcpf(sxx);
+        const float al = dx * rsxx, be = -sxy * rsxx;
+        const float zy0 = fmaf(iyy, dy0, ixy * dx);
+        const float c0 = fmaf(kHalfLog2e * al, dx, __builtin_amdgcn_logf(nrm));
+        const float c2 = kHalfLog2e * __builtin_amdgcn_rcpf(iyy);
+        float m0 = 0.f, m1 = 0.f, m2 = 0.f;
         static_for<0, C::CH>([&](auto rr) {
           constexpr int r = decltype(rr)::value;
-          const float dy = dy0 + (float)r;
-          const float zx = fmaf(ixy, dy, cx);
-          const float zy = fmaf(iyy, dy, cy);
-          const float gn = gv[r] * __builtin_amdgcn_exp2f(fmaf(dy, fmaf(e2, dy, e1), e0));
-          const float gx = gn * zx, gy = gn * zy;
-          a0 += gn;
-          ax += gx;
-          ay += gy;
-          axx = fmaf(gx, zx, axx);
-          axy = fmaf(gx, zy, axy);
-          ayy = fmaf(gy, zy, ayy);
+          const float zy = fmaf(iyy, (float)r, zy0);
+          const float gn = gv[r] * __builtin_amdgcn_exp2f(fmaf(c2 * zy, zy, c0));
+          const float gz = gn * zy;
+          m0 += gn;
+          m1 += gz;
+          m2 = fmaf(gz, zy, m2);
         });
+        // sum g N (1, zx, zy, zx^2, zx zy, zy^2) from the moments
+        float a0 = m0, ay = m1, ayy = m2;
+        float ax = fmaf(be, m1, al * m0);
+        float axy = fmaf(be, m2, al * m1);
+        float axx = fmaf(be, axy, al * ax);
         a0 = seg_sum<W>(a0, s_x2);
         ax = seg_sum<W>(ax, s_x2);
         ay = seg_sum<W>(ay, s_x2);
@@ -189,8 +194,14 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
       // t2 = exp(-2 pi i k / W) o2 = r u (TwFactor): e2 +- t2 as FMAs
       using T = TwFactor<-1, W, k>;
       const float2 u = T::unit(o2);
-      gr[y * (M + 1) + k] = make_float2(fmaf(T::r, u.x, e2.x), fmaf(T::r, u.y, e2.y));
-      if constexpr (2 * k != M) gr[y * (M + 1) + (M - k)] = make_float2(fmaf(-T::r, u.x, e2.x), fmaf(T::r, u.y, -e2.y));
+      if constexpr (k == 0) {
+        // Gr2[0] and Gr2[W/2] are real: stored packed as (Gr2[0], Gr2[W/2]) in
+        // column 0, which the column DFT transforms as one complex column
+        gr[y * (M + 1)] = make_float2(e2.x + u.x, e2.x - u.x);
+      } else {
+        gr[y * (M + 1) + k] = make_float2(fmaf(T::r, u.x, e2.x), fmaf(T::r, u.y, e2.y));
+        if constexpr (2 * k != M) gr[y * (M + 1) + (M - k)] = make_float2(fmaf(-T::r, u.x, e2.x), fmaf(T::r, u.y, -e2.y));
+      }
     });
   }
   __syncthreads();
@@ -203,14 +214,8 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
     const float sg = h ? -1.f : 1.f;
     static_for<0, M>([&](auto yy) {
       constexpr int yq = decltype(yy)::value;
-      float2 a, b;
-      if (c == 0) {
-        a = make_float2(gr[yq * (M + 1)].x, gr[yq * (M + 1) + M].x);
-        b = make_float2(gr[(yq + M) * (M + 1)].x, gr[(yq + M) * (M + 1) + M].x);
-      } else {
-        a = gr[yq * (M + 1) + c];
-        b = gr[(yq + M) * (M + 1) + c];
-      }
+      const float2 a = gr[yq * (M + 1) + c];  // c = 0: the packed (k_x = 0, k_x = W/2) pair
+      const float2 b = gr[(yq + M) * (M + 1) + c];
       const float2 v = make_float2(fmaf(sg, b.x, a.x), fmaf(sg, b.y, a.y));
       const float2 tw = twiddle<-1, W, yq>(v);  // exp(-2 pi i yq / W) v
       Gk[yq] = h ? tw : v;

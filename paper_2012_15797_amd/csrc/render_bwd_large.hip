@@ -100,24 +100,36 @@ render_bwd_w256_kernel(RenderArgs p, const float* __restrict__ gout, float* __re
         const float syy = fmaf(v, G.b22, p.pg[4]);
         const float det = fmaf(sxx, syy, -(sxy * sxy));
         const float rdet = __builtin_amdgcn_rcpf(det);
-        const float ixx = syy * rdet, ixy = -sxy * rdet, iyy = sxx * rdet;
+        const float ixy = -sxy * rdet, iyy = sxx * rdet;
         const float nrm = kInv2Pi * __builtin_amdgcn_rsqf(det);
         const float dyb = (float)ybase + dyc, dybw = dyb - (float)W;
-        float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        // Along this thread's column zy = ixy dx + iyy dy, zx = al + be zy
+        // (al = dx / sxx, be = -sxy / sxx) and q = dx al + zy^2 / iyy, so the
+        // column needs sum g N zy^p (p = 0, 1, 2) only; log2 of nrm exp(-q/2)
+        // is c0 + c2 zy^2.
+        const float rsxx = __builtin_amdgcn_rcpf(sxx);
+        const float al = dx * rsxx, be = -sxy * rsxx;
+        const float zyb = fmaf(iyy, dyb, ixy * dx), zybw = fmaf(iyy, dybw, ixy * dx);
+        const float c0 = fmaf(kHalfLog2e * al, dx, __builtin_amdgcn_logf(nrm));
+        const float c2 = kHalfLog2e * __builtin_amdgcn_rcpf(iyy);
+        float m0 = 0.f, m1 = 0.f, m2 = 0.f;
         static_for<0, RCH / 2>([&](auto rr) {
           constexpr int r = decltype(rr)::value;
-          const float dy = ((r >= rwrap) ? dybw : dyb) + (float)r;
-          const float zx = fmaf(ixx, dx, ixy * dy);
-          const float zy = fmaf(ixy, dx, iyy * dy);
-          const float gn = gv[r] * nrm * __builtin_amdgcn_exp2f(kHalfLog2e * fmaf(dx, zx, dy * zy));
-          const float gx = gn * zx, gy = gn * zy;
-          acc[0] += gn;
-          acc[1] += gx;
-          acc[2] += gy;
-          acc[3] = fmaf(gx, zx, acc[3]);
-          acc[4] = fmaf(gx, zy, acc[4]);
-          acc[5] = fmaf(gy, zy, acc[5]);
+          const float zy = fmaf(iyy, (float)r, (r >= rwrap) ? zybw : zyb);
+          const float gn = gv[r] * __builtin_amdgcn_exp2f(fmaf(c2 * zy, zy, c0));
+          const float gz = gn * zy;
+          m0 += gn;
+          m1 += gz;
+          m2 = fmaf(gz, zy, m2);
         });
+        // sum g N (1, zx, zy, zx^2, zx zy, zy^2) from the moments
+        float acc[6];
+        acc[0] = m0;
+        acc[2] = m1;
+        acc[5] = m2;
+        acc[1] = fmaf(be, m1, al * m0);
+        acc[4] = fmaf(be, m2, al * m1);
+        acc[3] = fmaf(be, acc[4], al * acc[1]);
         for (int i = 0; i < 6; ++i) {
           const float tot = block_sum512(acc[i], s_red);
           if (l == 0) s_racc[k][i] += tot;

@@ -124,6 +124,24 @@ def test_backward_routing_flags(ctx, flags):
     psf.close(); mix.close()
 
 
+@pytest.mark.parametrize("W", [16, 64, 128, 256])
+def test_backward_forced_real_each_size(ctx, W):
+    """Every component in real space (GFC_FORCE_REAL = 2): the adjoint's
+    pixel-space sums alone carry the shape, position and amplitude terms, at
+    each kernel's stamp size (the 256 kernel sums over 512 threads)."""
+    rng = np.random.Generator(np.random.PCG64(450 + W))
+    cfg = wl.config2(10)
+    n = 16 if W < 128 else 6
+    gal = wl.draw_galaxies(rng, n, W, (np.arange(n) % 2).astype(np.int32), r_e_range=(0.4, W / 5.0))
+    g = rng.standard_normal((n, W, W)).astype(np.float32)
+    psf, mix = lib_objects(ctx, cfg)
+    gp, ga = gpu_grads(ctx, psf, mix, gal, W, g, flags=2)
+    rp, ra = oracle_grads(cfg, gal, g, flags=2)
+    assert_close(gp, rp, f"params W={W} forced real")
+    assert_close(ga, ra, f"amplitudes W={W} forced real")
+    psf.close(); mix.close()
+
+
 def test_backward_fit_workload(ctx):
     """The differentiation workload: DEV8, 64x64, upstream gradient
     (I - T) / sigma^2 with T = render at perturbed parameters plus noise of
