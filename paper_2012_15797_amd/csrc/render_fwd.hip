@@ -96,6 +96,15 @@ render_small_kernel(RenderArgs p) {
       }
     });
   }
+  if constexpr (LZ) {
+    // The galaxy sits at its integer position (the fractional part is the
+    // Lanczos shift), and that integer shift is applied as a Fourier phase as
+    // well (cyclic shift theorem) instead of a roll at the store: the stamp
+    // then leaves the row transform in output order, so the filter's edges
+    // are fixed at compile time.
+    G.fx = (float)G.nx;
+    G.fy = (float)G.ny;
+  }
   const float* amp = p.amp + G.table * kKmax;
   const float* var = p.var + G.table * kKmax;
   const int kloop = C::WAVE1 ? G.K : p.kmax;
@@ -403,24 +412,22 @@ render_small_kernel(RenderArgs p) {
   const float dx = (float)l - G.x0 - pg[0];
   const float dyc = -G.y0 - pg[1];
   float* outp = p.out + (live ? stamp : 0) * (int64_t)(W * W);
-  const int colsrc = (l - G.nx) & (W - 1);
   if constexpr (LZ) {
     static_assert(W <= 64, "the fused shift keeps a whole column per lane");
     {
       // Lanczos-3 shift by the fractional position, fused into the store: a
       // lane keeps its whole output column (W <= 64), so the stamp makes one
-      // trip to memory.  The real-space components are added to the rows
+      // trip to memory.  The tile is in output order (the integer shift went
+      // into the phase).  The real-space components are added to the rows
       // first (the shift applies to the whole stamp), the rows are filtered
-      // along x while read from the LDS tile, the columns along y in
-      // registers.  Taps outside the stamp have weight zero.
+      // along x in the row-owning lane and written to the LDS tile, and the
+      // columns are filtered along y in registers as the tile's rows are
+      // read.  Taps outside the stamp have weight zero.
       if (rmask != 0) {
-        // Real-space components along this lane's tile row y, with exactly the
-        // arithmetic of the column-wise store (so that at integer positions,
-        // where the shift is the identity, both routes agree bit for bit).
-        const int yq = y / C::HR, yr = y - yq * C::HR;
-        const int ybase = (yq * C::HR + G.ny) & (W - 1);
-        const float dyb = (float)ybase + dyc;
-        const float dy = ((yr >= W - ybase) ? dyb - (float)W : dyb) + (float)yr;
+        // Real-space components along this lane's row: e(x) is a quadratic in
+        // the column x with per-row coefficients, two FMAs per pixel.
+        const float dy = (float)y + dyc;
+        const float dx0 = -G.x0 - pg[0];  // dx of column 0
         for (unsigned mk = rmask; mk != 0; mk &= mk - 1) {
           const float2 rs = s_rs[slot][__builtin_ctz(mk)];
           const float v = rs.x, ra = rs.y;
@@ -433,23 +440,19 @@ render_small_kernel(RenderArgs p) {
           const float c0 = kHalfLog2e * (syy * rdet);
           const float c1 = -2.f * kHalfLog2e * (sxy * rdet);
           const float a2 = kHalfLog2e * (sxx * rdet);
-          int nxc = G.nx;  // renewed per component: the columns' dx are recomputed rather than all held
-          if constexpr (C::WAVE1) asm volatile("" : "+s"(nxc));
-          else asm volatile("" : "+v"(nxc));
-          static_for<0, W>([&](auto xx) {
-            constexpr int x = decltype(xx)::value;
-            const float dxp = (float)((x + nxc) & (W - 1)) - G.x0 - pg[0];  // output column's dx
-            const float e = fmaf(dy, fmaf(a2, dy, c1 * dxp), c0 * dxp * dxp);
-            if constexpr (x & 1) R[x >> 1].y = fmaf(ampr, __builtin_amdgcn_exp2f(e), R[x >> 1].y);
-            else R[x >> 1].x = fmaf(ampr, __builtin_amdgcn_exp2f(e), R[x >> 1].x);
+          // e = c0 dx^2 + c1 dx dy + a2 dy^2 with dx = x + dx0
+          const float q2 = c0;
+          const float q1 = fmaf(2.f * c0, dx0, c1 * dy);
+          const float q0 = fmaf(dx0, fmaf(c0, dx0, c1 * dy), a2 * dy * dy);
+          static_for<0, W / 2>([&](auto xx) {
+            constexpr int x = 2 * decltype(xx)::value;  // two columns at a time
+            const float e0 = fmaf((float)x, fmaf(q2, (float)x, q1), q0);
+            const float e1 = fmaf((float)(x + 1), fmaf(q2, (float)(x + 1), q1), q0);
+            R[x >> 1].x = fmaf(ampr, __builtin_amdgcn_exp2f(e0), R[x >> 1].x);
+            R[x >> 1].y = fmaf(ampr, __builtin_amdgcn_exp2f(e1), R[x >> 1].y);
           });
         }
       }
-      // Rows: the x filter in the row-owning lane (tile column x is output
-      // column (x + nx) mod W, so neighbours are cyclic in x, masked where
-      // they cross the stamp's edge), written to the LDS tile.  Columns: the
-      // y filter as the tile's rows are read, each source row added into the
-      // output rows it feeds.
       float acc[W];
       static_for<0, W>([&](auto tt) { acc[decltype(tt)::value] = 0.f; });
       static_for<0, 2>([&](auto qq) {
@@ -459,48 +462,41 @@ render_small_kernel(RenderArgs p) {
           asm volatile("" : "+v"(row));
           static_for<0, W>([&](auto xx) {
             constexpr int x = decltype(xx)::value;
-            const int X = (x + G.nx) & (W - 1);
             float hsum = 0.f;
             static_for<0, 6>([&](auto dd) {
               constexpr int d = decltype(dd)::value;
-              constexpr int xs = (x + d - 3) & (W - 1);
-              const float in = (xs & 1) ? R[xs >> 1].y : R[xs >> 1].x;
-              const int Xs = X + d - 3;
-              hsum = fmaf((Xs >= 0 && Xs < W) ? wxn[d] : 0.f, in, hsum);
+              constexpr int xs = x + d - 3;
+              if constexpr (xs >= 0 && xs < W) hsum = fmaf(wxn[d], (xs & 1) ? R[xs >> 1].y : R[xs >> 1].x, hsum);
             });
             st[row + x] = hsum;
           });
         }
         __syncthreads();
         static_for<0, C::HR>([&](auto rr) {
-          constexpr int sr = q * C::HR + decltype(rr)::value;  // source tile row
-          const float v = st[(sr - q * C::HR) * (W + 1) + colsrc];
+          constexpr int sr = q * C::HR + decltype(rr)::value;  // source row
+          const float v = st[(sr - q * C::HR) * (W + 1) + l];
           static_for<0, 6>([&](auto dd) {
             constexpr int d = decltype(dd)::value;
-            constexpr int t = (sr - d + 3 + W) & (W - 1);  // output tile row fed through tap d
-            const int ys = ((t + G.ny) & (W - 1)) + d - 3;
-            acc[t] = fmaf((ys >= 0 && ys < W) ? wy[d] : 0.f, v, acc[t]);
+            constexpr int t = sr - d + 3;  // output row fed through tap d
+            if constexpr (t >= 0 && t < W) acc[t] = fmaf(wy[d], v, acc[t]);
           });
-          // Output row t is complete once its sources t - 3 .. t + 2 are in:
-          // rows 3 .. W/2 - 3 during the first pass, rows W/2 - 2 .. W - 3
-          // during the second, and rows W - 2, W - 1, 0, 1, 2 (whose sources
-          // wrap around) at the end.
+          // Output row t is complete once its sources t - 3 .. t + 2 within
+          // the stamp are in; the last two rows after the final source row.
           constexpr int done = sr - 2;
-          if constexpr ((q == 0 && done >= 3) || q == 1) {
-            if (live) __builtin_nontemporal_store(acc[done], outp + ((done + G.ny) & (W - 1)) * W + l);
+          if constexpr (done >= 0) {
+            if (live) __builtin_nontemporal_store(acc[done], outp + done * W + l);
           }
           __builtin_amdgcn_sched_barrier(0);
         });
         __syncthreads();
       });
       if (live) {
-        static_for<0, 5>([&](auto ii) {
-          constexpr int t = (W - 2 + decltype(ii)::value) & (W - 1);
-          __builtin_nontemporal_store(acc[t], outp + ((t + G.ny) & (W - 1)) * W + l);
-        });
+        __builtin_nontemporal_store(acc[W - 2], outp + (W - 2) * W + l);
+        __builtin_nontemporal_store(acc[W - 1], outp + (W - 1) * W + l);
       }
     }
   } else {
+    const int colsrc = (l - G.nx) & (W - 1);
     static_for<0, 2>([&](auto qq) {
       constexpr int q = decltype(qq)::value;
       if (y / C::HR == q) {

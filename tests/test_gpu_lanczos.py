@@ -90,17 +90,29 @@ def test_lanczos_with_forced_routing(ctx, extra):
     psf.close(); mix.close()
 
 
-def test_integer_positions_match_the_fourier_route_bitwise(ctx):
-    """At integer positions the shift weights are (0, 0, 0, 1, 0, 0): the
-    Lanczos route returns exactly the Fourier-phase render."""
-    cfg = wl.config_metric(50)
-    gal = cfg["gal"]
+@pytest.mark.parametrize("W", [16, 32, 64, 128])
+def test_integer_positions_match_the_fourier_route(ctx, W):
+    """At integer positions the shift weights are (0, 0, 0, 1, 0, 0), so the
+    Lanczos route returns the Fourier-phase render.  At W <= 64 the Lanczos
+    kernel applies the integer shift as a Fourier phase (cyclic shift
+    theorem) where the plain route rolls the stamp, so the two agree to the
+    rounding of that phase: within 2e-6 of each stamp's peak, far below the
+    1e-5 parity bar.  At 128 the separate shift pass after the plain render
+    is exact."""
+    cfg = wl.config_metric(50) if W == 64 else wl.config2(50)
+    rng = np.random.Generator(np.random.PCG64(700 + W))
+    gal = cfg["gal"] if W == 64 else wl.draw_galaxies(rng, 50, W, 0, r_e_range=(0.4, W / 6.0))
     gal.x[:] = np.floor(gal.x)
     gal.y[:] = np.floor(gal.y)
     psf, mix = lib_objects(ctx, cfg)
-    a = render_gpu(ctx, psf, mix, gal, 64)
-    b = render_gpu(ctx, psf, mix, gal, 64, flags=LZ)
-    assert np.array_equal(a, b)
+    a = render_gpu(ctx, psf, mix, gal, W)
+    b = render_gpu(ctx, psf, mix, gal, W, flags=LZ)
+    if W == 128:
+        assert np.array_equal(a, b)
+    else:
+        peak = np.abs(a).reshape(len(gal), -1).max(axis=1)
+        err = np.abs(a - b).reshape(len(gal), -1).max(axis=1)
+        assert (err <= 2e-6 * peak).all(), float((err / peak).max())
     psf.close(); mix.close()
 
 
