@@ -43,9 +43,12 @@ struct LargeCfg {
   static constexpr int XPT = BLOCK / W;   // threads per output column in the store (1 or 2)
   static constexpr int PASSES = RCH / (RPL * XPT);
   static constexpr int SLAB = (NC + 1) * W;  // float2 per stamp in the scratch slab
-  // LDS: combine chunk = CCH*D*M float2; store chunk = 2 halves x RCH x M float2
-  static constexpr int LDS_F2 = CCH * D * M;
-  static_assert(LDS_F2 == 2 * RCH * M, "shared buffer sizes differ");
+  // Rows of M float2 are M + 1 apart in LDS: a wavefront's lanes each write
+  // their own row, and an odd stride puts those rows in different banks.
+  static constexpr int MP = M + 1;
+  // LDS: combine chunk = CCH*D rows; store chunk = 2 halves x RCH rows
+  static constexpr int LDS_F2 = CCH * D * MP;
+  static_assert(LDS_F2 == 2 * RCH * MP, "shared buffer sizes differ");
   static_assert(W == 128 || W == 256, "stamp sizes 128 and 256");
   static_assert(XPT * W == BLOCK && NR * BLOCK == NL, "thread counts");
   static_assert((NC / CCH) == 2 * NR && (W / RCH) == 2 * NR, "two combine and two store chunks per round");
@@ -69,8 +72,8 @@ template <int W, bool EIG>
 __global__ void __launch_bounds__(LargeCfg<W>::BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
 render_large_kernel(RenderArgs p, float2* __restrict__ scratch) {
   using C = LargeCfg<W>;
-  constexpr int D = C::D, M = C::M, NC = C::NC, NL = C::NL, BLOCK = C::BLOCK, NR = C::NR, CCH = C::CCH,
-                RCH = C::RCH, RPL = C::RPL, SLAB = C::SLAB, LDS_F2 = C::LDS_F2;
+  constexpr int D = C::D, M = C::M, MP = C::MP, NC = C::NC, NL = C::NL, BLOCK = C::BLOCK, NR = C::NR,
+                CCH = C::CCH, RCH = C::RCH, RPL = C::RPL, SLAB = C::SLAB, LDS_F2 = C::LDS_F2;
   __shared__ float2 s_buf[LDS_F2];
   __shared__ float2 s_py[W + 2];
   __shared__ float2 s_nyq[W];
@@ -261,7 +264,7 @@ render_large_kernel(RenderArgs p, float2* __restrict__ scratch) {
       static_for<0, 2>([&](auto tt) {
         constexpr int tc = 2 * rd + decltype(tt)::value;  // chunk: columns 32 tc .. 32 tc + 31
         if ((c / CCH) == tc) {
-          const int base = ((c % CCH) * D + h) * M;
+          const int base = ((c % CCH) * D + h) * MP;
           static_for<0, M>([&](auto jj) {
             constexpr int jx = decltype(jj)::value;
             s_buf[base + jx] = Z[jx];
@@ -271,8 +274,8 @@ render_large_kernel(RenderArgs p, float2* __restrict__ scratch) {
         static_for<0, CCH / (BLOCK / M)>([&](auto bb) {
           constexpr int b = decltype(bb)::value;
           const int cl = wv + b * (BLOCK / M);
-          const float2* e = &s_buf[(cl * D) * M + j];
-          const float2 t0 = e[0], t1 = cmul(w1, e[M]), t2 = cmul(w2, e[2 * M]), t3 = cmul(w3, e[3 * M]);
+          const float2* e = &s_buf[(cl * D) * MP + j];
+          const float2 t0 = e[0], t1 = cmul(w1, e[MP]), t2 = cmul(w2, e[2 * MP]), t3 = cmul(w3, e[3 * MP]);
           const float2 a = cadd(t0, t2), bq = csub(t0, t2), cq = cadd(t1, t3), d = rot90<+1>(csub(t1, t3));
           const float2 x0 = cadd(a, cq), x1 = cadd(bq, d), x2 = csub(a, cq), x3 = csub(bq, d);
           const int cg = tc * CCH + cl;
@@ -345,7 +348,7 @@ render_large_kernel(RenderArgs p, float2* __restrict__ scratch) {
         constexpr int tc = 2 * rr + decltype(tt)::value;  // chunk: rows 64 tc .. 64 tc + 63
         if ((wl >> 1) == tc) {
           // tile [q][row - 64 tc][n]
-          float2* dst = &s_buf[(q * RCH + (y - tc * RCH)) * M];
+          float2* dst = &s_buf[(q * RCH + (y - tc * RCH)) * MP];
           static_for<0, M>([&](auto ii) {
             constexpr int i = decltype(ii)::value;
             dst[i] = Rq[i];
@@ -375,8 +378,8 @@ render_large_kernel(RenderArgs p, float2* __restrict__ scratch) {
           static_for<0, RPL>([&](auto rq) {
             constexpr int r = decltype(rq)::value;
             const int srow = srowb + r;
-            const float z0 = tile[2 * (srow * M + nn) + (odd ? 1 : 0)];
-            const float2 z1 = s_buf[(RCH + srow) * M + nn];
+            const float z0 = tile[2 * (srow * MP + nn) + (odd ? 1 : 0)];
+            const float2 z1 = s_buf[(RCH + srow) * MP + nn];
             val[r] = fmaf(ca, z1.x, fmaf(cb, z1.y, z0));
           });
           const int srow0 = tc * RCH + srowb;
