@@ -317,6 +317,16 @@ render_small_kernel(RenderArgs p) {
   // omega = -1/2 is the conjugate of row W/2 (omega = +1/2).
   float sy, cy;
   sincospi_poly(-2.f * G.fy * omN, &sy, &cy);
+  if constexpr (!LZ) {
+    // The integer part of the y centre goes into the phase as well:
+    // exp(-2 pi i n_y k_y / W) for row k_y = l (mod W) is an exact table
+    // entry.  The stamp then leaves the transforms in output row order, and
+    // only its columns are rolled at the store.
+    const float2 ti = twiddle_rt<-1, W>(G.ny * l);
+    const float c2 = fmaf(cy, ti.x, -(sy * ti.y)), s2 = fmaf(cy, ti.y, sy * ti.x);
+    cy = c2;
+    sy = s2;
+  }
   float sxa, cxa;
   sincospi_poly(h ? -G.fx : -2.f * G.fx * nu, &sxa, &cxa);
   const float sx = pair_even(sxa), cx = pair_even(cxa);
@@ -514,8 +524,6 @@ render_small_kernel(RenderArgs p) {
         constexpr int r = decltype(rr)::value;
         val[r] = st[r * (W + 1) + colsrc];
       });
-      const int ybase = (q * C::HR + G.ny) & (W - 1);  // output row of r = 0
-      const int rwrap = W - ybase;                      // rows r >= rwrap wrap to the top
       if (rmask != 0) {
         for (unsigned mk = rmask; mk != 0; mk &= mk - 1) {
           const float2 rs = s_rs[slot][__builtin_ctz(mk)];  // LDS, not global: no wait on the stores above
@@ -529,18 +537,19 @@ render_small_kernel(RenderArgs p) {
           const float a0 = kHalfLog2e * (syy * rdet) * dx * dx;
           const float a1 = -2.f * kHalfLog2e * (sxy * rdet) * dx;
           const float a2 = kHalfLog2e * (sxx * rdet);
-          const float dyb = (float)ybase + dyc;
-          const float dybw = dyb - (float)W;
+          // e = a0 + dy (a1 + a2 dy) with dy = dyq + r, as a quadratic in the
+          // tile row r: e0 + r (e1 + a2 r), two FMAs with an immediate r
+          const float dyq = (float)(q * C::HR) + dyc;
+          const float e0 = fmaf(dyq, fmaf(a2, dyq, a1), a0);
+          const float e1 = fmaf(2.f * a2, dyq, a1);
           // two rows at a time, so that each exponential has an independent
           // instruction between it and its use
           static_for<0, C::HR / 2>([&](auto rr) {
             constexpr int r = 2 * decltype(rr)::value;
-            const float dy0 = ((r >= rwrap) ? dybw : dyb) + (float)r;
-            const float dy1 = ((r + 1 >= rwrap) ? dybw : dyb) + (float)(r + 1);
-            const float g0 = __builtin_amdgcn_exp2f(fmaf(dy0, fmaf(a2, dy0, a1), a0));
-            const float g1 = __builtin_amdgcn_exp2f(fmaf(dy1, fmaf(a2, dy1, a1), a0));
-            val[r] = fmaf(ampr, g0, val[r]);
-            val[r + 1] = fmaf(ampr, g1, val[r + 1]);
+            const float x0 = (r == 0) ? e0 : fmaf((float)r, fmaf(a2, (float)r, e1), e0);
+            const float x1 = fmaf((float)(r + 1), fmaf(a2, (float)(r + 1), e1), e0);
+            val[r] = fmaf(ampr, __builtin_amdgcn_exp2f(x0), val[r]);
+            val[r + 1] = fmaf(ampr, __builtin_amdgcn_exp2f(x1), val[r + 1]);
           });
         }
       }
@@ -548,14 +557,13 @@ render_small_kernel(RenderArgs p) {
         if (p.flags & kAccumulate) {
           static_for<0, C::HR>([&](auto rr) {
             constexpr int r = decltype(rr)::value;
-            float* rowp = outp + ((ybase + r) & (W - 1)) * W;
+            float* rowp = outp + (q * C::HR + r) * W;
             __builtin_nontemporal_store(val[r] + rowp[l], &rowp[l]);
           });
         } else {
           static_for<0, C::HR>([&](auto rr) {
             constexpr int r = decltype(rr)::value;
-            float* rowp = outp + ((ybase + r) & (W - 1)) * W;  // uniform when one stamp per wavefront
-            __builtin_nontemporal_store(val[r], &rowp[l]);     // streamed output
+            __builtin_nontemporal_store(val[r], outp + (q * C::HR + r) * W + l);  // streamed output
           });
         }
       }
