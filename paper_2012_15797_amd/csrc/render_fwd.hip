@@ -16,9 +16,10 @@
 //                is applied while reading back.
 //  row phase     lane y owns row y and runs the length-W complex-to-real
 //                inverse transform as a W/2-point complex FFT in registers.
-//  store         rows go through LDS with the integer part of the centre
-//                applied as a cyclic roll, then real-space components
-//                (step 8) are added and stamps are written coalesced.
+//  store         rows go through LDS with the integer part of the x centre
+//                applied as a cyclic roll (the integer part of y is a phase
+//                in the y-phase table), then real-space components (step 8)
+//                are added and stamps are written coalesced.
 #include "gfc_device.hpp"
 #include "gfc_launch.hpp"
 
