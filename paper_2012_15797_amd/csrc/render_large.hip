@@ -21,8 +21,10 @@
 //                complex-to-real row transform (a 128-point complex FFT split
 //                into two 64-point FFTs); the split is uniform per wavefront.
 //  store         64 rows at a time through LDS: the last radix-2 stage of the
-//                row transform, the integer roll of the centre and the
-//                real-space components (step 8), then coalesced stores.
+//                row transform, the integer roll of the x centre (the integer
+//                y shift is a phase in the y-phase table, so rows arrive in
+//                output order) and the real-space components (step 8), then
+//                coalesced stores.
 #include "gfc_device.hpp"
 #include "gfc_launch.hpp"
 
@@ -207,6 +209,14 @@ render_large_kernel(RenderArgs p, float2* __restrict__ scratch) {
         }
         float sy, cy, sxh, cxh;
         sincospi_poly(-2.f * G.fy * omN, &sy, &cy);
+        {
+          // the integer part of the y centre as a phase too (an exact table
+          // entry): the stamp leaves the transforms in output row order
+          const float2 ti = twiddle_rt<-1, W>(G.ny * t);
+          const float c2 = fmaf(cy, ti.x, -(sy * ti.y)), s2 = fmaf(cy, ti.y, sy * ti.x);
+          cy = c2;
+          sy = s2;
+        }
         sincospi_poly(-G.fx, &sxh, &cxh);
         s_py[t] = make_float2(cy, sy);
         if (t == W / 2) s_py[W] = make_float2(cy, -sy);
@@ -395,16 +405,22 @@ render_large_kernel(RenderArgs p, float2* __restrict__ scratch) {
             const float a0 = kHalfLog2e * (syy * rdet) * dx * dx;
             const float a1 = -2.f * kHalfLog2e * (sxy * rdet) * dx;
             const float a2 = kHalfLog2e * (sxx * rdet);
-            static_for<0, RPL>([&](auto rq) {
-              constexpr int r = decltype(rq)::value;
-              const int Y = (srow0 + r + G.ny) & (W - 1);
-              const float dy = (float)Y - G.y0 - pg[1];
-              val[r] = fmaf(ampr, __builtin_amdgcn_exp2f(fmaf(dy, fmaf(a2, dy, a1), a0)), val[r]);
+            // output row srow0 + r: the exponent a0 + dy (a1 + a2 dy) as a
+            // quadratic in r, two FMAs with an immediate per pixel
+            const float dyq = (float)srow0 - G.y0 - pg[1];
+            const float e0 = fmaf(dyq, fmaf(a2, dyq, a1), a0);
+            const float e1 = fmaf(2.f * a2, dyq, a1);
+            static_for<0, RPL / 2>([&](auto rq) {
+              constexpr int r = 2 * decltype(rq)::value;
+              const float x0 = (r == 0) ? e0 : fmaf((float)r, fmaf(a2, (float)r, e1), e0);
+              const float x1 = fmaf((float)(r + 1), fmaf(a2, (float)(r + 1), e1), e0);
+              val[r] = fmaf(ampr, __builtin_amdgcn_exp2f(x0), val[r]);
+              val[r + 1] = fmaf(ampr, __builtin_amdgcn_exp2f(x1), val[r + 1]);
             });
           }
           static_for<0, RPL>([&](auto rq) {
             constexpr int r = decltype(rq)::value;
-            const int Y = (srow0 + r + G.ny) & (W - 1);
+            const int Y = srow0 + r;
             const float v = (p.flags & kAccumulate) ? val[r] + outp[Y * W + X] : val[r];
             __builtin_nontemporal_store(v, &outp[Y * W + X]);  // streamed output
           });
