@@ -174,18 +174,20 @@ def test_large_workload_full_size_sampled(ctx):
     psf.close(); mix.close()
 
 
-@pytest.mark.parametrize("W", [64, 256])
+@pytest.mark.parametrize("W", [16, 32, 64, 128, 256])
 def test_edge_positions_and_integer_shift(ctx, W):
     """Centres near and across the stamp edge, negative and large
-    coordinates (the integer part becomes a cyclic roll of the Fourier
-    image); every component forced to Fourier space so the roll is exact."""
-    cfg = wl.config_metric(8)
+    coordinates: the integer part of x becomes a cyclic roll of the Fourier
+    image and that of y a phase from an exact table entry.  Run with every
+    component forced to Fourier space, so the whole stamp is periodic, and
+    with the hybrid routing."""
+    cfg = wl.config_metric(10)
     base = cfg["gal"]
     s = W / 64.0
-    xs = (np.array([0.0, 0.4, 63.9, -3.25, 100.6, 31.0, 32.5, -64.2]) * s).astype(np.float32)
-    ys = (np.array([63.7, 0.0, 17.2, 5.5, -40.1, 31.0, 96.0, 2.0]) * s).astype(np.float32)
+    xs = (np.array([0.0, 0.4, 63.9, -3.25, 100.6, 31.0, 32.5, -64.2, 12345.625, -9876.5]) * s).astype(np.float32)
+    ys = (np.array([63.7, 0.0, 17.2, 5.5, -40.1, 31.0, 96.0, 2.0, -23456.375, 8765.125]) * s).astype(np.float32)
     gal = wl.Galaxies(xs, ys, base.flux, base.r_e, base.e1, base.e2, base.mix_id,
-                      np.full(8, W, np.int32))
+                      np.full(10, W, np.int32))
     psf, mix = lib_objects(ctx, cfg)
     for flags in (o.FORCE_FOURIER, 0):
         gpu = render_gpu(ctx, psf, mix, gal, W, flags=flags)
