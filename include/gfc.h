@@ -276,14 +276,32 @@ gfc_status gfc_server_poll(gfc_server* srv, uint64_t ticket, int* done, const fl
 gfc_status gfc_server_wait(gfc_server* srv, uint64_t ticket, int timeout_ms,
                            const float** out_dev);
 /* Copies a finished request's stamps (n*W*W float32) into dst (device),
- * asynchronously on hip_stream.  GFC_EBUSY if the request is not done. */
+ * asynchronously on hip_stream.  GFC_EBUSY if the request is not done.  The
+ * request may be released right after: the server reuses its memory only
+ * once the copy has completed. */
 gfc_status gfc_server_copy(gfc_server* srv, uint64_t ticket, float* dst, void* hip_stream);
-/* Returns the request's device memory to the budget. */
+/* Returns the request's device memory to the budget.  Work the caller
+ * enqueued itself on the request's stamps (through out_dev) must have
+ * completed before the call; copies made with gfc_server_copy need not. */
 gfc_status gfc_server_release(gfc_server* srv, uint64_t ticket);
 /* Latency (submit -> completion) percentiles over completed requests, and
  * stamps completed per second of server lifetime; also launches issued. */
 gfc_status gfc_server_stats(gfc_server* srv, double* p50_ms, double* p99_ms, double* max_ms,
                             double* stamps_per_s, uint64_t* n_launches, uint64_t* n_done);
+/* Open-loop load generator, for measuring a server without a client in the
+ * way: request i (reqs[i], as for gfc_server_submit, copied at submission)
+ * is submitted at t0 + t_arrive[i] seconds, t0 being the call's start, from
+ * the calling thread; a second host thread waits for the requests in
+ * submission order and releases each as soon as it completes.  Returns when
+ * every submitted request is released.  t_arrive: host, n doubles, finite,
+ * non-negative, non-decreasing.  lag: host, n doubles receiving how late
+ * each submission was (seconds), or NULL.  span_s: seconds from t0 to the
+ * last completion, or NULL.  Latencies are then in gfc_server_stats.  A
+ * rejected submission stops the replay (GFC_EREJECTED after draining); a
+ * failed request gives its status.  Not to be called concurrently with
+ * other submissions to the same server. */
+gfc_status gfc_server_replay(gfc_server* srv, const gfc_request* reqs, const double* t_arrive,
+                             int64_t n, double* lag, double* span_s);
 /* Drains every queued request, then frees the server. */
 gfc_status gfc_server_destroy(gfc_server* srv);
 

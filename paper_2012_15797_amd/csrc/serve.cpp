@@ -16,11 +16,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <iterator>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -66,6 +68,8 @@ struct Batch {
   // device executor state
   void* mem = nullptr;
   hipEvent_t event = nullptr;
+  std::vector<hipEvent_t> reads;  // copies out of `mem` on callers' streams (gfc_server_copy)
+  size_t arena_off = 0, arena_size = 0;  // `mem` is arena_size bytes of the server's arena (0: its own allocation)
 };
 
 class Executor {
@@ -175,6 +179,10 @@ class Core {
     auto it = reqs_.find(t);
     return it == reqs_.end() ? nullptr : it->second.get();
   }
+  Batch* batch(uint64_t id) {
+    auto it = batches_.find(id);
+    return it == batches_.end() ? nullptr : it->second.get();
+  }
 
   gfc_status release(uint64_t t) {
     Req* r = find(t);
@@ -265,7 +273,7 @@ class Core {
 // ---------------------------------------------------------------- device executor
 class HipExecutor : public Executor {
  public:
-  HipExecutor(gfc_ctx* ctx, int n_streams) : ctx_(ctx) {
+  HipExecutor(gfc_ctx* ctx, int n_streams, size_t budget) : ctx_(ctx) {
     DeviceGuard g(ctx_->device);
     streams_.resize(std::max(1, n_streams), nullptr);
     events_.resize(streams_.size(), nullptr);
@@ -274,6 +282,19 @@ class HipExecutor : public Executor {
     for (auto& s : streams_) hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
     // one completion event per stream: a stream holds at most one batch in flight
     for (auto& e : events_) hipEventCreateWithFlags(&e, hipEventDisableTiming);
+    // Batch memory comes from one device arena the size of the budget (at
+    // most 80% of the free memory): a stream-ordered allocation per batch
+    // cost up to several milliseconds of host time each under load.
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
+      const size_t want = std::min(budget, free_b / 10 * 8) & ~(size_t)(kAlign - 1);
+      void* p = nullptr;
+      if (want >= ((size_t)1 << 20) && hipMalloc(&p, want) == hipSuccess) {
+        arena_ = static_cast<char*>(p);
+        arena_bytes_ = want;
+        free_[0] = want;
+      }
+    }
   }
   ~HipExecutor() override {
     DeviceGuard g(ctx_->device);
@@ -281,6 +302,12 @@ class HipExecutor : public Executor {
       hipStreamSynchronize(s);
       hipStreamDestroy(s);
     }
+    for (auto& pd : pending_)
+      for (hipEvent_t ev : pd.reads) {
+        hipEventSynchronize(ev);
+        hipEventDestroy(ev);
+      }
+    if (arena_) hipFree(arena_);
     for (auto p : staging_)
       if (p) hipHostFree(p);
     for (auto e : events_)
@@ -315,7 +342,11 @@ class HipExecutor : public Executor {
       else
         std::memcpy(hm + r->offset, r->mix_id.data(), r->n * sizeof(int32_t));
     }
-    if (hipMallocAsync(&b.mem, out_bytes + par_bytes, s) != hipSuccess) {
+    b.arena_size = 0;
+    if (void* m = arena_alloc(out_bytes + par_bytes, &b.arena_off)) {
+      b.mem = m;
+      b.arena_size = align(out_bytes + par_bytes);
+    } else if (hipMallocAsync(&b.mem, out_bytes + par_bytes, s) != hipSuccess) {  // arena full or fragmented
       b.mem = nullptr;
       for (Req* r : b.reqs) r->status = GFC_ENOMEM;
       return -1;
@@ -353,6 +384,22 @@ class HipExecutor : public Executor {
   }
   void release(Batch& b) override {
     DeviceGuard g(ctx_->device);
+    if (b.arena_size) {
+      // The batch has finished, so only callers' copies can still read the
+      // block: it is free now, or once those copies have completed.
+      if (b.reads.empty()) arena_free(b.arena_off, b.arena_size);
+      else pending_.push_back(Pending{b.arena_off, b.arena_size, std::move(b.reads)});
+      b.reads.clear();
+      b.arena_size = 0;
+      b.mem = nullptr;
+    }
+    // stream-ordered allocation: reused in this stream's order, so first wait
+    // for the copies callers made from it on their own streams
+    for (hipEvent_t ev : b.reads) {
+      hipStreamWaitEvent(streams_[b.stream], ev, 0);
+      hipEventDestroy(ev);
+    }
+    b.reads.clear();
     if (b.mem) hipFreeAsync(b.mem, streams_[b.stream]);
     b.mem = nullptr;
     b.event = nullptr;
@@ -368,6 +415,64 @@ class HipExecutor : public Executor {
   std::vector<hipEvent_t> events_;
   std::vector<void*> staging_;
   std::vector<size_t> staging_bytes_;
+
+  // ---- batch memory arena (guarded by the server lock, like every executor call)
+  static constexpr size_t kAlign = 256;
+  struct Pending {
+    size_t off, size;
+    std::vector<hipEvent_t> reads;  // the block is free once these have completed
+  };
+  static size_t align(size_t n) { return (n + kAlign - 1) & ~(kAlign - 1); }
+  // First fit over the free blocks (offset -> size); nullptr if nothing fits.
+  void* arena_alloc(size_t bytes, size_t* off) {
+    if (!arena_) return nullptr;
+    reclaim();
+    bytes = align(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < bytes) continue;
+      const size_t o = it->first, rest = it->second - bytes;
+      free_.erase(it);
+      if (rest) free_[o + bytes] = rest;
+      *off = o;
+      return arena_ + o;
+    }
+    return nullptr;
+  }
+  // Returns a block, merging it with free neighbours.
+  void arena_free(size_t off, size_t bytes) {
+    auto next = free_.lower_bound(off);
+    if (next != free_.end() && off + bytes == next->first) {
+      bytes += next->second;
+      next = free_.erase(next);
+    }
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += bytes;
+        return;
+      }
+    }
+    free_[off] = bytes;
+  }
+  // Frees the pending blocks whose callers' copies have completed.
+  void reclaim() {
+    for (size_t i = 0; i < pending_.size();) {
+      bool done = true;
+      for (hipEvent_t ev : pending_[i].reads) done = done && hipEventQuery(ev) != hipErrorNotReady;
+      if (!done) {
+        ++i;
+        continue;
+      }
+      for (hipEvent_t ev : pending_[i].reads) hipEventDestroy(ev);
+      arena_free(pending_[i].off, pending_[i].size);
+      pending_[i] = std::move(pending_.back());
+      pending_.pop_back();
+    }
+  }
+  char* arena_ = nullptr;
+  size_t arena_bytes_ = 0;
+  std::map<size_t, size_t> free_;
+  std::vector<Pending> pending_;
 };
 
 // ---------------------------------------------------------------- callback executor
@@ -440,7 +545,7 @@ gfc_status gfc_server_create(gfc_ctx* ctx, size_t mem_budget_bytes, int n_stream
   auto* s = new (std::nothrow) gfc_server();
   if (!s) return fail(GFC_ENOMEM, "server allocation failed");
   s->ctx = ctx;
-  s->ex = std::make_unique<HipExecutor>(ctx, n_streams);
+  s->ex = std::make_unique<HipExecutor>(ctx, n_streams, mem_budget_bytes);
   s->core = std::make_unique<Core>(s->ex.get(), mem_budget_bytes, n_streams, max_batch_stamps);
   s->worker = std::thread(server_loop, s);
   ctx->n_objects++;
@@ -519,6 +624,18 @@ gfc_status gfc_server_copy(gfc_server* s, uint64_t ticket, float* dst, void* hip
   hipError_t e = hipMemcpyAsync(dst, r->out_ptr, (size_t)r->n * r->W * r->W * sizeof(float),
                                 hipMemcpyDeviceToDevice, (hipStream_t)hip_stream);
   if (e != hipSuccess) return hip_fail(e, "copy of request stamps");
+  // the batch's memory is freed only after this copy (see HipExecutor::release)
+  hipEvent_t ev = nullptr;
+  e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(ev, (hipStream_t)hip_stream);
+  if (e != hipSuccess) {
+    if (ev) hipEventDestroy(ev);
+    hipStreamSynchronize((hipStream_t)hip_stream);  // no event: finish the copy here instead
+    return GFC_OK;
+  }
+  Batch* b = s->core->batch(r->batch);
+  if (b) b->reads.push_back(ev);
+  else hipEventDestroy(ev);
   return GFC_OK;
 }
 
@@ -535,6 +652,68 @@ gfc_status gfc_server_stats(gfc_server* s, double* p50_ms, double* p99_ms, doubl
   if (!s) return fail(GFC_EINVAL, "null server");
   std::lock_guard<std::mutex> lock(s->mu);
   s->core->stats(p50_ms, p99_ms, max_ms, stamps_per_s, n_launches, n_done);
+  return GFC_OK;
+}
+
+gfc_status gfc_server_replay(gfc_server* s, const gfc_request* reqs, const double* t_arrive, int64_t n,
+                             double* lag, double* span_s) {
+  if (!s || n < 0 || (n > 0 && (!reqs || !t_arrive))) return fail(GFC_EINVAL, "null argument or negative count");
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(t_arrive[i]) || t_arrive[i] < 0.0 || (i > 0 && t_arrive[i] < t_arrive[i - 1]))
+      return fail(GFC_EINVAL, "arrival times must be finite, non-negative and non-decreasing");
+  using clock = std::chrono::steady_clock;
+  std::vector<uint64_t> tickets((size_t)n);
+  std::mutex m;
+  std::condition_variable cv;
+  int64_t submitted = 0;  // guarded by m
+  bool stopped = false;   // guarded by m: no further submissions
+  gfc_status wait_st = GFC_OK;
+  double t_last = 0.0;
+  const clock::time_point t0 = clock::now();
+  // Completions in submission order: wait, then release at once.
+  std::thread waiter([&] {
+    for (int64_t i = 0; i < n; ++i) {
+      {
+        std::unique_lock<std::mutex> lk(m);
+        cv.wait(lk, [&] { return submitted > i || stopped; });
+        if (submitted <= i) return;
+      }
+      const gfc_status st = gfc_server_wait(s, tickets[(size_t)i], -1, nullptr);
+      if (st != GFC_OK && wait_st == GFC_OK) wait_st = st;
+      t_last = std::chrono::duration<double>(clock::now() - t0).count();
+      gfc_server_release(s, tickets[(size_t)i]);
+    }
+  });
+  gfc_status sub_st = GFC_OK;
+  for (int64_t i = 0; i < n; ++i) {
+    const clock::time_point target =
+        t0 + std::chrono::duration_cast<clock::duration>(std::chrono::duration<double>(t_arrive[i]));
+    for (;;) {  // sleep to within 0.3 ms of the arrival, then spin
+      const clock::time_point now = clock::now();
+      if (now >= target) break;
+      if (target - now > std::chrono::microseconds(500))
+        std::this_thread::sleep_for(target - now - std::chrono::microseconds(300));
+    }
+    if (lag) lag[i] = std::chrono::duration<double>(clock::now() - target).count();
+    uint64_t tk = 0;
+    sub_st = gfc_server_submit(s, &reqs[i], &tk);
+    if (sub_st != GFC_OK) break;
+    {
+      std::lock_guard<std::mutex> lk(m);
+      tickets[(size_t)i] = tk;
+      submitted = i + 1;
+    }
+    cv.notify_one();
+  }
+  {
+    std::lock_guard<std::mutex> lk(m);
+    stopped = true;
+  }
+  cv.notify_one();
+  waiter.join();
+  if (span_s) *span_s = t_last;
+  if (sub_st != GFC_OK) return fail(sub_st, "a replayed request was not accepted");
+  if (wait_st != GFC_OK) return fail(wait_st, "a replayed request failed");
   return GFC_OK;
 }
 

@@ -144,35 +144,14 @@ class Scheduler:
 
 
 def replay_trace(server, requests, psfs, mix, flags=0):
-    """Open-loop client for a request trace: each request (dict with t [s],
-    psf index, W, gal) is submitted at its arrival time on the host clock; a
-    second thread waits for completions in submission order and releases
-    each request at once.  Returns server-side latency percentiles (submit to
-    observed completion), throughput over the trace, and the submission lag
-    behind the schedule."""
-    import queue
-    import threading
-    import time
-
+    """Open-loop replay of a request trace (dicts with t [s], psf index, W,
+    gal) against a server with the library's native load generator
+    (gfc_server_replay): submissions at the arrival times and in-order
+    waits and releases run on host threads of their own, so the Python
+    interpreter does not pace the trace.  Returns server-side latency
+    percentiles (submit to completion observed by the server), throughput
+    over the trace, and the submission lag behind the schedule."""
     n_req = len(requests)
-    tickets = [0] * n_req
-    lag = np.zeros(n_req)
-    q: "queue.Queue" = queue.Queue()
-    t_last = [0.0]
-    err = []
-
-    def waiter():
-        while True:
-            i = q.get()
-            if i is None:
-                return
-            try:
-                server.wait(tickets[i])
-                t_last[0] = time.perf_counter()
-                server.release(tickets[i])
-            except Exception as e:  # noqa: BLE001 - reported after the run
-                err.append(e)
-
     prepared = []
     stamps = 0
     for r in requests:
@@ -180,27 +159,15 @@ def replay_trace(server, requests, psfs, mix, flags=0):
         prepared.append(server.prepare(psfs[r["psf"]], mix, r["W"], g.x, g.y, g.flux, g.r_e, g.e1, g.e2,
                                        mix_id=g.mix_id, flags=flags))
         stamps += len(g)
-    th = threading.Thread(target=waiter, daemon=True)
-    th.start()
-    t0 = time.perf_counter()
-    for i, r in enumerate(requests):
-        target = t0 + r["t"]
-        while True:
-            d = target - time.perf_counter()
-            if d <= 0:
-                break
-            if d > 5e-4:
-                time.sleep(d - 3e-4)
-        lag[i] = time.perf_counter() - target
-        tickets[i] = server.submit_prepared(prepared[i])
-        q.put(i)
-    q.put(None)
-    th.join()
-    if err:
-        raise err[0]
+    reqs = (gfc_request * n_req)(*[p[0] for p in prepared])
+    t_arr = np.ascontiguousarray([r["t"] for r in requests], np.float64)
+    lag = np.zeros(n_req, np.float64)
+    span = ctypes.c_double()
+    D_p = ctypes.POINTER(ctypes.c_double)
+    call("gfc_server_replay", server.handle, reqs, t_arr.ctypes.data_as(D_p), n_req, lag.ctypes.data_as(D_p),
+         ctypes.byref(span))
     st = server.stats()
-    span = t_last[0] - t0
     return dict(requests=n_req, stamps=stamps, offered_rate_hz=n_req / max(requests[-1]["t"], 1e-9),
                 p50_ms=round(st["p50_ms"], 4), p99_ms=round(st["p99_ms"], 4), max_ms=round(st["max_ms"], 4),
-                stamps_per_s=round(stamps / span, 1), launches=st["launches"],
+                stamps_per_s=round(stamps / max(span.value, 1e-9), 1), launches=st["launches"],
                 submit_lag_p99_ms=round(float(np.percentile(lag, 99)) * 1e3, 4))

@@ -102,3 +102,45 @@ def test_plain_mode_and_trace_replay(ctx):
         if max_batch == 0:
             assert res["launches"] == res["requests"]
         srv.close()
+
+
+def test_native_replay_errors(ctx):
+    """gfc_server_replay validates the arrival times before submitting
+    anything, and stops at a rejected request after draining the ones it
+    submitted (the server stays usable)."""
+    import ctypes
+
+    import paper_2012_15797_amd as gfc
+    from paper_2012_15797_amd._lib import call, gfc_request
+    from paper_2012_15797_amd.serving import Server
+
+    tr = wl.config4_trace(duration_s=0.05, rate_hz=2000.0, restricted=True)
+    psfs, mix = _objects(ctx, tr, 1)
+    g = wl.draw_galaxies(np.random.Generator(np.random.PCG64(3)), 64, 64, 0)
+    srv = Server(ctx, mem_budget_bytes=8 << 20, n_streams=1)
+    small = srv.prepare(psfs[0], mix, 64, g.x[:8], g.y[:8], g.flux[:8], g.r_e[:8], g.e1[:8], g.e2[:8])
+    big = srv.prepare(psfs[0], mix, 64, g.x, g.y, g.flux, g.r_e, g.e1, g.e2)  # 64 stamps: 1 MB, fits
+    huge_g = wl.draw_galaxies(np.random.Generator(np.random.PCG64(4)), 1024, 64, 0)  # 16 MB > budget
+    huge = srv.prepare(psfs[0], mix, 64, huge_g.x, huge_g.y, huge_g.flux, huge_g.r_e, huge_g.e1, huge_g.e2)
+    D_p = ctypes.POINTER(ctypes.c_double)
+
+    def replay(items, times):
+        reqs = (gfc_request * len(items))(*[p[0] for p in items])
+        t = np.ascontiguousarray(times, np.float64)
+        lag = np.zeros(len(items))
+        call("gfc_server_replay", srv.handle, reqs, t.ctypes.data_as(D_p), len(items), lag.ctypes.data_as(D_p), None)
+        return lag
+
+    with pytest.raises(gfc.GfcError) as e:
+        replay([small, small], [0.002, 0.001])
+    assert e.value.status == -1
+    with pytest.raises(gfc.GfcError) as e:
+        replay([small, big, huge, small], [0.0, 0.0, 0.001, 0.001])
+    assert e.value.status == -6
+    lag = replay([small, big, small], [0.0, 0.0005, 0.001])  # still usable; every request released
+    assert (lag >= 0).all() and lag.max() < 0.5
+    assert srv.stats()["done"] == 5  # two before the rejection, three after
+    srv.close()
+    for p in psfs:
+        p.close()
+    mix.close()
