@@ -261,7 +261,10 @@ typedef struct {
  * (outputs + parameters: n * (4 W^2 + 28) bytes each); max_batch_stamps:
  * most stamps fused into one launch (<= 0: one launch per request, the plain
  * mode); n_streams: concurrent launch streams (1..8).  The policy is that of
- * the scheduling core below.  A background thread launches and reaps. */
+ * the scheduling core below.  A background thread launches and reaps.  The
+ * server reserves its budget (at most 80% of the device's free memory) as one
+ * device allocation at creation and places batches in it; when that is
+ * fragmented a batch takes a stream-ordered allocation instead. */
 gfc_status gfc_server_create(gfc_ctx* ctx, size_t mem_budget_bytes, int n_streams,
                              int64_t max_batch_stamps, gfc_server** out);
 /* Queues a request; returns at once with a ticket.  GFC_EREJECTED if the
