@@ -150,6 +150,103 @@ render_small_kernel(RenderArgs p) {
   qn[0] = fmaf(omN, fmaf(qd, omN, qb), qa);      // (+1/2, omN)
   qn[1] = fmaf(omN, fmaf(qd, omN, -qb), qa);     // (-1/2, omN)
 
+  // PSF spectrum of this lane's bins and the PSF Gaussian (step 2; for a
+  // varying PSF, the weighted sum of the components at the galaxy's image
+  // position, whose transforms and moments are linear in the weights).
+  float2 Pm[M];
+  float2 psfN;
+  float pg[6];
+  // With a varying PSF (W <= 64) the components' spectra are summed before
+  // the mixture loop, while its sums are not yet live (more registers for
+  // the LDS reads in flight); otherwise the spectrum is formed after it.
+  constexpr bool kPsfFirst = EIG && W <= 64;
+  auto psf_terms = [&]() {
+    if constexpr (EIG) {
+      const int64_t g = live ? stamp : p.n - 1;
+      float u = (p.psf_px[g] - p.eig_norm[0]) * p.eig_norm[1];
+      float v = (p.psf_py[g] - p.eig_norm[2]) * p.eig_norm[3];
+      if constexpr (C::WAVE1) {
+        u = uniform_f(u);
+        v = uniform_f(v);
+      }
+      const float up[4] = {1.f, u, u * u, u * u * u}, vp[4] = {1.f, v, v * v, v * v * v};
+      static_for<0, M>([&](auto mm) { Pm[decltype(mm)::value] = make_float2(0.f, 0.f); });
+      psfN = make_float2(0.f, 0.f);
+      float mom[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      if constexpr (C::SHARE) {
+        // Component j (its main bins, then its Nyquist column: contiguous in
+        // the cache) is copied into one half of the workgroup's transpose
+        // buffers, which are free until the column FFT, while the four
+        // wavefronts sum component j - 1 from the other half.  Reading a half
+        // again two components later is ordered by the barrier in between.
+        constexpr int NS = M * W + W;                   // float2 per component
+        constexpr int NV = NS / 2;                      // float4 per component
+        constexpr int PER = (NV + C::BLOCK - 1) / C::BLOCK;
+        static_assert(2 * NS <= C::SPB * C::T1N, "two component spectra fit in the transpose buffers");
+        float2* buf = &s_t1[0][0];
+        const float4* src = reinterpret_cast<const float4*>(p.psf_main);
+        const int64_t sv = p.eig_stride / 2;  // float4 from one component to the next
+        // staged float4 i of this thread: index threadIdx.x + i BLOCK, clamped
+        // (the last group is partial; clamped lanes re-read and skip the store)
+        float4 st0, st1, st2, st3, st4;
+        static_assert(PER == 5, "five float4 per thread at 64 x 64");
+        const int i4 = min((int)threadIdx.x + 4 * C::BLOCK, NV - 1);
+        const bool w4 = (int)threadIdx.x + 4 * C::BLOCK < NV;
+        const float4* s0 = src + threadIdx.x;
+        st0 = s0[0]; st1 = s0[C::BLOCK]; st2 = s0[2 * C::BLOCK]; st3 = s0[3 * C::BLOCK]; st4 = src[i4];
+        for (int j = 0; j < p.eig_J; ++j) {
+          float4* dst = reinterpret_cast<float4*>(buf + (j & 1) * NS) + threadIdx.x;
+          dst[0] = st0; dst[C::BLOCK] = st1; dst[2 * C::BLOCK] = st2; dst[3 * C::BLOCK] = st3;
+          if (w4) dst[4 * C::BLOCK] = st4;
+          __syncthreads();
+          if (j + 1 < p.eig_J) {  // in flight while component j is summed
+            const float4* sj = src + (j + 1) * sv;
+            st0 = sj[threadIdx.x]; st1 = sj[threadIdx.x + C::BLOCK]; st2 = sj[threadIdx.x + 2 * C::BLOCK];
+            st3 = sj[threadIdx.x + 3 * C::BLOCK]; st4 = sj[i4];
+          }
+          const float cj = eigen_weight(p, j, up, vp);
+          const float2* pj = buf + (j & 1) * NS;
+          static_for<0, M>([&](auto mm) {
+            constexpr int m = decltype(mm)::value;
+            const float2 q = pj[m * W + l];
+            Pm[m] = make_float2(fmaf(cj, q.x, Pm[m].x), fmaf(cj, q.y, Pm[m].y));
+          });
+          const float2 qn = pj[M * W + l];
+          psfN = make_float2(fmaf(cj, qn.x, psfN.x), fmaf(cj, qn.y, psfN.y));
+          static_for<0, 6>([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            mom[i] = fmaf(cj, p.eig_mom[j * 6 + i], mom[i]);
+          });
+        }
+      } else {
+        for (int j = 0; j < p.eig_J; ++j) {
+          const float cj = eigen_weight(p, j, up, vp);
+          const float2* pj = p.psf_main + j * p.eig_stride;
+          static_for<0, M>([&](auto mm) {
+            constexpr int m = decltype(mm)::value;
+            const float2 q = pj[m * W + l];
+            Pm[m] = make_float2(fmaf(cj, q.x, Pm[m].x), fmaf(cj, q.y, Pm[m].y));
+          });
+          const float2 qn = p.psf_nyq[j * p.eig_stride + l];
+          psfN = make_float2(fmaf(cj, qn.x, psfN.x), fmaf(cj, qn.y, psfN.y));
+          static_for<0, 6>([&](auto ii) {
+            constexpr int i = decltype(ii)::value;
+            mom[i] = fmaf(cj, p.eig_mom[j * 6 + i], mom[i]);
+          });
+        }
+      }
+      eigen_gauss(mom, pg);
+    } else {
+      static_for<0, M>([&](auto mm) {
+        constexpr int m = decltype(mm)::value;
+        Pm[m] = p.psf_main[m * W + l];
+      });
+      psfN = p.psf_nyq[l];
+      static_for<0, 6>([&](auto ii) { pg[decltype(ii)::value] = p.pg[decltype(ii)::value]; });
+    }
+  };
+  if constexpr (kPsfFirst) psf_terms();
+
   // Component 0 initialises the sums (every table has one; with zero Fourier
   // weight it contributes zeros), the rest accumulate.
   float S[M + 1];
@@ -221,95 +318,7 @@ render_small_kernel(RenderArgs p) {
     }
   }
 
-  // PSF spectrum of this lane's bins and the PSF Gaussian (step 2; for a
-  // varying PSF, the weighted sum of the components at the galaxy's image
-  // position, whose transforms and moments are linear in the weights).
-  float2 Pm[M];
-  float2 psfN;
-  float pg[6];
-  if constexpr (EIG) {
-    const int64_t g = live ? stamp : p.n - 1;
-    float u = (p.psf_px[g] - p.eig_norm[0]) * p.eig_norm[1];
-    float v = (p.psf_py[g] - p.eig_norm[2]) * p.eig_norm[3];
-    if constexpr (C::WAVE1) {
-      u = uniform_f(u);
-      v = uniform_f(v);
-    }
-    const float up[4] = {1.f, u, u * u, u * u * u}, vp[4] = {1.f, v, v * v, v * v * v};
-    static_for<0, M>([&](auto mm) { Pm[decltype(mm)::value] = make_float2(0.f, 0.f); });
-    psfN = make_float2(0.f, 0.f);
-    float mom[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    if constexpr (C::SHARE) {
-      // Component j (its main bins, then its Nyquist column: contiguous in
-      // the cache) is copied into one half of the workgroup's transpose
-      // buffers, which are free until the column FFT, while the four
-      // wavefronts sum component j - 1 from the other half.  Reading a half
-      // again two components later is ordered by the barrier in between.
-      constexpr int NS = M * W + W;                   // float2 per component
-      constexpr int NV = NS / 2;                      // float4 per component
-      constexpr int PER = (NV + C::BLOCK - 1) / C::BLOCK;
-      static_assert(2 * NS <= C::SPB * C::T1N, "two component spectra fit in the transpose buffers");
-      float2* buf = &s_t1[0][0];
-      const float4* src = reinterpret_cast<const float4*>(p.psf_main);
-      const int64_t sv = p.eig_stride / 2;  // float4 from one component to the next
-      // staged float4 i of this thread: index threadIdx.x + i BLOCK, clamped
-      // (the last group is partial; clamped lanes re-read and skip the store)
-      float4 st0, st1, st2, st3, st4;
-      static_assert(PER == 5, "five float4 per thread at 64 x 64");
-      const int i4 = min((int)threadIdx.x + 4 * C::BLOCK, NV - 1);
-      const bool w4 = (int)threadIdx.x + 4 * C::BLOCK < NV;
-      const float4* s0 = src + threadIdx.x;
-      st0 = s0[0]; st1 = s0[C::BLOCK]; st2 = s0[2 * C::BLOCK]; st3 = s0[3 * C::BLOCK]; st4 = src[i4];
-      for (int j = 0; j < p.eig_J; ++j) {
-        float4* dst = reinterpret_cast<float4*>(buf + (j & 1) * NS) + threadIdx.x;
-        dst[0] = st0; dst[C::BLOCK] = st1; dst[2 * C::BLOCK] = st2; dst[3 * C::BLOCK] = st3;
-        if (w4) dst[4 * C::BLOCK] = st4;
-        __syncthreads();
-        if (j + 1 < p.eig_J) {  // in flight while component j is summed
-          const float4* sj = src + (j + 1) * sv;
-          st0 = sj[threadIdx.x]; st1 = sj[threadIdx.x + C::BLOCK]; st2 = sj[threadIdx.x + 2 * C::BLOCK];
-          st3 = sj[threadIdx.x + 3 * C::BLOCK]; st4 = sj[i4];
-        }
-        const float cj = eigen_weight(p, j, up, vp);
-        const float2* pj = buf + (j & 1) * NS;
-        static_for<0, M>([&](auto mm) {
-          constexpr int m = decltype(mm)::value;
-          const float2 q = pj[m * W + l];
-          Pm[m] = make_float2(fmaf(cj, q.x, Pm[m].x), fmaf(cj, q.y, Pm[m].y));
-        });
-        const float2 qn = pj[M * W + l];
-        psfN = make_float2(fmaf(cj, qn.x, psfN.x), fmaf(cj, qn.y, psfN.y));
-        static_for<0, 6>([&](auto ii) {
-          constexpr int i = decltype(ii)::value;
-          mom[i] = fmaf(cj, p.eig_mom[j * 6 + i], mom[i]);
-        });
-      }
-    } else {
-      for (int j = 0; j < p.eig_J; ++j) {
-        const float cj = eigen_weight(p, j, up, vp);
-        const float2* pj = p.psf_main + j * p.eig_stride;
-        static_for<0, M>([&](auto mm) {
-          constexpr int m = decltype(mm)::value;
-          const float2 q = pj[m * W + l];
-          Pm[m] = make_float2(fmaf(cj, q.x, Pm[m].x), fmaf(cj, q.y, Pm[m].y));
-        });
-        const float2 qn = p.psf_nyq[j * p.eig_stride + l];
-        psfN = make_float2(fmaf(cj, qn.x, psfN.x), fmaf(cj, qn.y, psfN.y));
-        static_for<0, 6>([&](auto ii) {
-          constexpr int i = decltype(ii)::value;
-          mom[i] = fmaf(cj, p.eig_mom[j * 6 + i], mom[i]);
-        });
-      }
-    }
-    eigen_gauss(mom, pg);
-  } else {
-    static_for<0, M>([&](auto mm) {
-      constexpr int m = decltype(mm)::value;
-      Pm[m] = p.psf_main[m * W + l];
-    });
-    psfN = p.psf_nyq[l];
-    static_for<0, 6>([&](auto ii) { pg[decltype(ii)::value] = p.pg[decltype(ii)::value]; });
-  }
+  if constexpr (!kPsfFirst) psf_terms();
 
   // Fractional-shift phases (shift theorem): exp(-2 pi i (fx nu + fy om)).
   // Every lane evaluates the y phase of row l and one x phase: lanes h = 0
