@@ -170,9 +170,11 @@ render_small_kernel(RenderArgs p) {
         v = uniform_f(v);
       }
       const float up[4] = {1.f, u, u * u, u * u * u}, vp[4] = {1.f, v, v * v, v * v * v};
-      static_for<0, M>([&](auto mm) { Pm[decltype(mm)::value] = make_float2(0.f, 0.f); });
-      psfN = make_float2(0.f, 0.f);
       float mom[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      if constexpr (!C::SHARE) {
+        static_for<0, M>([&](auto mm) { Pm[decltype(mm)::value] = make_float2(0.f, 0.f); });
+        psfN = make_float2(0.f, 0.f);
+      }
       if constexpr (C::SHARE) {
         // Component j (its main bins, then its Nyquist column: contiguous in
         // the cache) is copied into one half of the workgroup's transpose
@@ -206,13 +208,21 @@ render_small_kernel(RenderArgs p) {
           }
           const float cj = eigen_weight(p, j, up, vp);
           const float2* pj = buf + (j & 1) * NS;
-          static_for<0, M>([&](auto mm) {
-            constexpr int m = decltype(mm)::value;
-            const float2 q = pj[m * W + l];
-            Pm[m] = make_float2(fmaf(cj, q.x, Pm[m].x), fmaf(cj, q.y, Pm[m].y));
-          });
-          const float2 qn = pj[M * W + l];
-          psfN = make_float2(fmaf(cj, qn.x, psfN.x), fmaf(cj, qn.y, psfN.y));
+          if (j == 0) {  // the first component initialises the sums (eig_J >= 1)
+            static_for<0, M>([&](auto mm) {
+              constexpr int m = decltype(mm)::value;
+              Pm[m] = cscale(pj[m * W + l], cj);
+            });
+            psfN = cscale(pj[M * W + l], cj);
+          } else {
+            static_for<0, M>([&](auto mm) {
+              constexpr int m = decltype(mm)::value;
+              const float2 q = pj[m * W + l];
+              Pm[m] = make_float2(fmaf(cj, q.x, Pm[m].x), fmaf(cj, q.y, Pm[m].y));
+            });
+            const float2 qn = pj[M * W + l];
+            psfN = make_float2(fmaf(cj, qn.x, psfN.x), fmaf(cj, qn.y, psfN.y));
+          }
           static_for<0, 6>([&](auto ii) {
             constexpr int i = decltype(ii)::value;
             mom[i] = fmaf(cj, p.eig_mom[j * 6 + i], mom[i]);
