@@ -144,3 +144,42 @@ def test_native_replay_errors(ctx):
     for p in psfs:
         p.close()
     mix.close()
+
+
+def test_release_right_after_copy_keeps_the_copy(ctx):
+    """A request released right after gfc_server_copy was enqueued on a busy
+    stream: the server must not hand its memory to the next batch before
+    the copy has read it.  The copy's stream is held up by a spin kernel
+    while a second request of the same size renders."""
+    import torch
+    from paper_2012_15797_amd.serving import Server
+
+    tr = wl.config4_trace(duration_s=0.01, rate_hz=2000.0, restricted=True)
+    psfs, mix = _objects(ctx, tr, 1)
+    rng = np.random.Generator(np.random.PCG64(11))
+    g1 = wl.draw_galaxies(rng, 512, 64, 0)
+    g2 = wl.draw_galaxies(rng, 512, 64, 0)
+    # budget for one request at a time: the second batch would take the first's block
+    one = 512 * (64 * 64 * 4 + 28)
+    srv = Server(ctx, mem_budget_bytes=one + 4096, n_streams=1)
+    t1 = srv.submit(psfs[0], mix, 64, g1.x, g1.y, g1.flux, g1.r_e, g1.e1, g1.e2)
+    srv.wait(t1)
+    side = torch.cuda.Stream()
+    out1 = torch.empty((512, 64, 64), device="cuda")
+    with torch.cuda.stream(side):
+        torch.cuda._sleep(50_000_000)  # hold the copy back
+        srv.result(t1, out=out1)
+    srv.release(t1)
+    t2 = srv.submit(psfs[0], mix, 64, g2.x, g2.y, g2.flux, g2.r_e, g2.e1, g2.e2)
+    srv.wait(t2)
+    side.synchronize()
+    ref1 = _direct(ctx, psfs[0], mix, dict(gal=g1, W=64))
+    assert torch.equal(out1, ref1)
+    out2 = srv.result(t2)
+    torch.cuda.synchronize()
+    assert torch.equal(out2, _direct(ctx, psfs[0], mix, dict(gal=g2, W=64)))
+    srv.release(t2)
+    srv.close()
+    for p in psfs:
+        p.close()
+    mix.close()
