@@ -186,8 +186,9 @@ typedef struct {
  * hip_stream.  out: device, n*W*W float32 [n][W][W].  Galaxies with invalid
  * parameters get an all-NaN stamp and increment the invalid counter; the
  * call itself does not synchronise.  n == 0 is a no-op.  W = 256 takes a
- * stream-ordered device slab of 264 KiB per resident workgroup (one per CU,
- * at most n) inside the call. */
+ * stream-ordered device slab of 264 KiB per resident workgroup (as many as
+ * the device keeps resident, two per CU on MI355X, at most n) inside the
+ * call. */
 gfc_status gfc_render_stamps(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix* mix,
                              const gfc_galaxies* gal, int64_t n, int W, unsigned flags,
                              float* out, void* hip_stream);
