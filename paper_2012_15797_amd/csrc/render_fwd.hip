@@ -160,6 +160,10 @@ render_small_kernel(RenderArgs p) {
   // the mixture loop, while its sums are not yet live (more registers for
   // the LDS reads in flight); otherwise the spectrum is formed after it.
   constexpr bool kPsfFirst = EIG && W <= 64;
+  // At 128 a constant PSF's spectrum (64 bins per lane) is read in the PSF
+  // product itself, 16 bins at a time, rather than all at once while the
+  // mixture sums are live.
+  constexpr bool kPsfStream = !EIG && W == 128;
   auto psf_terms = [&]() {
     if constexpr (EIG) {
       const int64_t g = live ? stamp : p.n - 1;
@@ -247,10 +251,12 @@ render_small_kernel(RenderArgs p) {
       }
       eigen_gauss(mom, pg);
     } else {
-      static_for<0, M>([&](auto mm) {
-        constexpr int m = decltype(mm)::value;
-        Pm[m] = p.psf_main[m * W + l];
-      });
+      if constexpr (!kPsfStream) {
+        static_for<0, M>([&](auto mm) {
+          constexpr int m = decltype(mm)::value;
+          Pm[m] = p.psf_main[m * W + l];
+        });
+      }
       psfN = p.psf_nyq[l];
       static_for<0, 6>([&](auto ii) { pg[decltype(ii)::value] = p.pg[decltype(ii)::value]; });
     }
@@ -370,7 +376,9 @@ render_small_kernel(RenderArgs p) {
   float2 Z[M];
   static_for<0, M>([&](auto mm) {
     constexpr int m = decltype(mm)::value;
-    const float2 P = Pm[m];
+    float2 P;
+    if constexpr (kPsfStream) P = p.psf_main[m * W + l];
+    else P = Pm[m];
     if constexpr (2 * m == W / 2) {
       const float2 q0 = s_py[slot][W / 2 + h];
       const float2 pyA = h ? q0 : cscale(q0, 0.5f);
@@ -379,6 +387,7 @@ render_small_kernel(RenderArgs p) {
     } else {
       Z[m] = cscale(cmul(cmul(P, s_py[slot][2 * m + h]), pxF), S[m]);
     }
+    if constexpr (kPsfStream && m % 16 == 15) __builtin_amdgcn_sched_barrier(0);  // bounds the loads in flight
   });
   if (c == 0) {  // column 0 carries the Nyquist column as its imaginary part
     static_for<0, M>([&](auto mm) {
