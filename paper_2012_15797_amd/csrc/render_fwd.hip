@@ -160,10 +160,11 @@ render_small_kernel(RenderArgs p) {
   // the mixture loop, while its sums are not yet live (more registers for
   // the LDS reads in flight); otherwise the spectrum is formed after it.
   constexpr bool kPsfFirst = EIG && W <= 64;
-  // At 128 a constant PSF's spectrum (64 bins per lane) is read in the PSF
-  // product itself, 16 bins at a time, rather than all at once while the
-  // mixture sums are live.
-  constexpr bool kPsfStream = !EIG && W == 128;
+  // At 64 and 128 a constant PSF's spectrum is read in the PSF product
+  // itself, 16 bins at a time, rather than all at once while the mixture
+  // sums are live: 144 -> 116 VGPRs at 64 (four wavefronts per SIMD instead
+  // of three), no spill at 128.
+  constexpr bool kPsfStream = !EIG && W >= 64;
   auto psf_terms = [&]() {
     if constexpr (EIG) {
       const int64_t g = live ? stamp : p.n - 1;
