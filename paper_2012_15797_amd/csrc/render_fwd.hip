@@ -493,6 +493,20 @@ render_small_kernel(RenderArgs p) {
           });
         }
       }
+      // x filter of this lane's row, with every lane active (in the staging
+      // passes below only half the lanes write, and arithmetic there would
+      // be issued once per pass)
+      float hrow[W];
+      static_for<0, W>([&](auto xx) {
+        constexpr int x = decltype(xx)::value;
+        float hsum = 0.f;
+        static_for<0, 6>([&](auto dd) {
+          constexpr int d = decltype(dd)::value;
+          constexpr int xs = x + d - 3;
+          if constexpr (xs >= 0 && xs < W) hsum = fmaf(wxn[d], (xs & 1) ? R[xs >> 1].y : R[xs >> 1].x, hsum);
+        });
+        hrow[x] = hsum;
+      });
       float acc[W];
       static_for<0, W>([&](auto tt) { acc[decltype(tt)::value] = 0.f; });
       static_for<0, 2>([&](auto qq) {
@@ -502,13 +516,7 @@ render_small_kernel(RenderArgs p) {
           asm volatile("" : "+v"(row));
           static_for<0, W>([&](auto xx) {
             constexpr int x = decltype(xx)::value;
-            float hsum = 0.f;
-            static_for<0, 6>([&](auto dd) {
-              constexpr int d = decltype(dd)::value;
-              constexpr int xs = x + d - 3;
-              if constexpr (xs >= 0 && xs < W) hsum = fmaf(wxn[d], (xs & 1) ? R[xs >> 1].y : R[xs >> 1].x, hsum);
-            });
-            st[row + x] = hsum;
+            st[row + x] = hrow[x];
           });
         }
         __syncthreads();
