@@ -33,13 +33,19 @@ struct PerGalaxyTables {
   int32_t* id;   // [n]: the galaxy's own index, or -1 if its profile is invalid
 };
 
+// The per-galaxy tables are written one thread per (galaxy, component)
+// element, so a wavefront's stores are contiguous ([n][kKmax] row-major);
+// the galaxy's scalars are read by its kKmax threads from one cache line.
+
 // Piecewise-linear interpolation in n of each component's amplitude and
 // variance between the two grid indices around n.
 __global__ void __launch_bounds__(kPre) sersic_tables_kernel(const float* __restrict__ sersic_n, int S,
                                                              const float* __restrict__ grid, int K, int64_t n,
                                                              PerGalaxyTables t) {
-  const int64_t g = (int64_t)blockIdx.x * kPre + threadIdx.x;
-  if (g >= n) return;
+  const int64_t e = (int64_t)blockIdx.x * kPre + threadIdx.x;
+  if (e >= n * kKmax) return;
+  const int64_t g = e / kKmax;
+  const int k = (int)(e % kKmax);
   const float* amp = grid + S;
   const float* var = amp + S * K;
   const float nn = sersic_n[g];
@@ -48,17 +54,17 @@ __global__ void __launch_bounds__(kPre) sersic_tables_kernel(const float* __rest
   for (int i = 1; i < S - 1; ++i)
     if (grid[i] <= nn) s = i;
   const float t1 = ok ? (nn - grid[s]) / (grid[s + 1] - grid[s]) : 0.f, t0 = 1.f - t1;
-  for (int k = 0; k < kKmax; ++k) {
-    float a = 0.f, v = 1.f;
-    if (k < K) {
-      a = fmaf(t0, amp[s * K + k], t1 * amp[(s + 1) * K + k]);
-      v = fmaf(t0, var[s * K + k], t1 * var[(s + 1) * K + k]);
-    }
-    t.amp[g * kKmax + k] = a;
-    t.var[g * kKmax + k] = v;
+  float a = 0.f, v = 1.f;
+  if (k < K) {
+    a = fmaf(t0, amp[s * K + k], t1 * amp[(s + 1) * K + k]);
+    v = fmaf(t0, var[s * K + k], t1 * var[(s + 1) * K + k]);
   }
-  t.K[g] = K;
-  t.id[g] = ok ? (int32_t)g : -1;
+  t.amp[e] = a;
+  t.var[e] = v;
+  if (k == 0) {
+    t.K[g] = K;
+    t.id[g] = ok ? (int32_t)g : -1;
+  }
 }
 
 // One-ellipticity composite: disk components with amplitudes (1 - f) A_d,
@@ -66,26 +72,30 @@ __global__ void __launch_bounds__(kPre) sersic_tables_kernel(const float* __rest
 __global__ void __launch_bounds__(kPre) composite_tables_kernel(
     const float* __restrict__ mamp, const float* __restrict__ mvar, int disk, int Kd, int bulge, int Kb,
     const float* __restrict__ frac, const float* __restrict__ rho, int64_t n, PerGalaxyTables t) {
-  const int64_t g = (int64_t)blockIdx.x * kPre + threadIdx.x;
-  if (g >= n) return;
+  const int64_t e = (int64_t)blockIdx.x * kPre + threadIdx.x;
+  if (e >= n * kKmax) return;
+  const int64_t g = e / kKmax;
+  const int k = (int)(e % kKmax);
   const float f = frac[g], r = rho[g];
   const bool ok = f >= 0.f && f <= 1.f && r > 0.f && __builtin_isfinite(r);
-  const float r2 = r * r;
-  for (int k = 0; k < kKmax; ++k) {
-    float a = 0.f, v = 1.f;
-    if (k < Kd) {
-      a = (1.f - f) * mamp[disk * kKmax + k];
-      v = mvar[disk * kKmax + k];
-    } else if (k < Kd + Kb) {
-      a = f * mamp[bulge * kKmax + (k - Kd)];
-      v = r2 * mvar[bulge * kKmax + (k - Kd)];
-    }
-    t.amp[g * kKmax + k] = a;
-    t.var[g * kKmax + k] = v;
+  float a = 0.f, v = 1.f;
+  if (k < Kd) {
+    a = (1.f - f) * mamp[disk * kKmax + k];
+    v = mvar[disk * kKmax + k];
+  } else if (k < Kd + Kb) {
+    a = f * mamp[bulge * kKmax + (k - Kd)];
+    v = (r * r) * mvar[bulge * kKmax + (k - Kd)];
   }
-  t.K[g] = Kd + Kb;
-  t.id[g] = ok ? (int32_t)g : -1;
+  t.amp[e] = a;
+  t.var[e] = v;
+  if (k == 0) {
+    t.K[g] = Kd + Kb;
+    t.id[g] = ok ? (int32_t)g : -1;
+  }
 }
+
+// Blocks for one thread per table element.
+inline unsigned table_blocks(int64_t n) { return (unsigned)((n * kKmax + kPre - 1) / kPre); }
 
 // Scratch for the per-galaxy tables, stream-ordered.
 gfc_status alloc_tables(int64_t n, hipStream_t s, void** block, PerGalaxyTables* t) {
@@ -210,7 +220,7 @@ gfc_status gfc_render_stamps_sersic(gfc_ctx* ctx, gfc_psf* psf, const gfc_sersic
   const int S = fam->S, K = fam->K;
   const float* grid = fam->d_grid;
   return render_per_galaxy(ctx, psf, &shell, K, gal, n, W, flags, out, s, [&](PerGalaxyTables t) {
-    hipLaunchKernelGGL(sersic_tables_kernel, dim3((unsigned)((n + kPre - 1) / kPre)), dim3(kPre), 0, s,
+    hipLaunchKernelGGL(sersic_tables_kernel, dim3(table_blocks(n)), dim3(kPre), 0, s,
                        sersic_n, S, grid, K, n, t);
     return hipGetLastError();
   });
@@ -231,7 +241,7 @@ gfc_status gfc_render_stamps_composite(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix
   const float* mamp = mix->d_amp;
   const float* mvar = mix->d_var;
   return render_per_galaxy(ctx, psf, mix, Kd + Kb, gal, n, W, flags, out, s, [&](PerGalaxyTables t) {
-    hipLaunchKernelGGL(composite_tables_kernel, dim3((unsigned)((n + kPre - 1) / kPre)), dim3(kPre), 0, s,
+    hipLaunchKernelGGL(composite_tables_kernel, dim3(table_blocks(n)), dim3(kPre), 0, s,
                        mamp, mvar, disk_table, Kd, bulge_table, Kb, bulge_frac, bulge_rho, n, t);
     return hipGetLastError();
   });
