@@ -235,7 +235,11 @@ gfc_status gfc_render_stamps_composite(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix
  * has a cone there).  workspace: device scratch of at least
  * gfc_backward_workspace_bytes(n) bytes, or NULL to let the library
  * allocate it per call.  W = 256 also takes a stream-ordered device slab of
- * 256 KiB per stamp (at most 1024 stamps at a time) inside the call.
+ * 256 KiB per stamp (at most 1024 stamps at a time) inside the call.  The
+ * workspace holds the partial sums of grad_amp for up to 16 tables; with
+ * more, they take a stream-ordered scratch of n_tables * ceil(n / 128) * 64
+ * bytes inside the call when that is at most 64 MiB (above it they are
+ * summed without one, more slowly).
  * Asynchronous on hip_stream. */
 size_t gfc_backward_workspace_bytes(int64_t n);
 gfc_status gfc_render_stamps_backward(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix* mix,

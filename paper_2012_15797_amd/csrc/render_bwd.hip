@@ -401,8 +401,63 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
   }
 }
 
-// grad_amp[t][k] += sum over galaxies i with table t of amp_part[i][k], in
-// index order within fixed 256-wide strides, then a fixed tree.
+// grad_amp[t][k] += sum over galaxies i with table t of amp_part[i][k]
+// (amp_part is [n][kKmax] row-major).  Every order below is fixed, so the
+// sums are the same from run to run.
+//
+// Two passes: the galaxies in chunks of kAgChunk, each (chunk, table) block
+// summing its rows with kAgRows threads per component (index order within a
+// thread, coalesced reads of whole rows) and a fixed tree over the threads;
+// then per table the chunk partials the same way.
+constexpr int kAgChunk = 128;
+constexpr int kAgRows = 256 / kKmax;
+
+__global__ void __launch_bounds__(256) amp_grad_partial(const float* __restrict__ amp_part,
+                                                        const int32_t* __restrict__ mix_id, int64_t n, int t0,
+                                                        int64_t nchunks, float* __restrict__ partial) {
+  const int64_t c = blockIdx.x;
+  const int t = t0 + (int)blockIdx.y;
+  const int r = threadIdx.x / kKmax, k = threadIdx.x % kKmax;
+  const int64_t i1 = min(n, (c + 1) * kAgChunk);
+  float acc = 0.f;
+#pragma unroll
+  for (int j = 0; j < kAgChunk / kAgRows; ++j) {  // the loads issue together; the adds stay in index order
+    const int64_t i = c * kAgChunk + r + j * kAgRows;
+    if (i < i1) {
+      const int ti = mix_id ? mix_id[i] : 0;
+      if (ti == t) acc += amp_part[i * kKmax + k];
+    }
+  }
+  __shared__ float s[256];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o >= kKmax; o >>= 1) {  // rows r and r + o / kKmax, same component
+    if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if ((int)threadIdx.x < kKmax) partial[((int64_t)t * nchunks + c) * kKmax + threadIdx.x] = s[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(256) amp_grad_finish(const float* __restrict__ partial, int64_t nchunks,
+                                                       float* __restrict__ grad_amp) {
+  const int t = blockIdx.x;
+  const int r = threadIdx.x / kKmax, k = threadIdx.x % kKmax;
+  float acc = 0.f;
+#pragma unroll 8
+  for (int64_t c = r; c < nchunks; c += kAgRows) acc += partial[((int64_t)t * nchunks + c) * kKmax + k];
+  __shared__ float s[256];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o >= kKmax; o >>= 1) {
+    if ((int)threadIdx.x < o) s[threadIdx.x] += s[threadIdx.x + o];
+    __syncthreads();
+  }
+  if ((int)threadIdx.x < kKmax) grad_amp[t * kKmax + threadIdx.x] += s[threadIdx.x];
+}
+
+// One pass per (table, component), for table counts whose chunk partials
+// would take more than 64 MiB: index order within fixed 256-wide strides,
+// then a fixed tree.
 __global__ void amp_grad_reduce(const float* __restrict__ amp_part, const int32_t* __restrict__ mix_id,
                                 int64_t n, float* __restrict__ grad_amp) {
   const int t = blockIdx.x / kKmax, k = blockIdx.x % kKmax;
@@ -452,10 +507,50 @@ static hipError_t launch_bwd_small(const RenderArgs& args, const float* gout, fl
 
 using namespace gfc;
 
+// Tables whose chunk partials the workspace holds (beyond that they take a
+// stream-ordered allocation).
+constexpr int kAgWsTables = 16;
+
+static int64_t amp_grad_chunks(int64_t n) { return (n + kAgChunk - 1) / kAgChunk; }
+
+// ws_partial: the workspace's room for kAgWsTables tables' partials.
+static hipError_t launch_amp_grad(const float* amp_part, const int32_t* mix_id, int64_t n, int n_tables,
+                                  float* grad_amp, float* ws_partial, hipStream_t s) {
+  const int64_t nchunks = amp_grad_chunks(n);
+  if ((int64_t)n_tables * nchunks > (int64_t)1 << 20) {
+    hipLaunchKernelGGL(amp_grad_reduce, dim3(n_tables * kKmax), dim3(256), 0, s, amp_part, mix_id, n, grad_amp);
+    return hipGetLastError();
+  }
+  float* partial = ws_partial;
+  hipError_t e = hipSuccess;
+  const bool own = n_tables > kAgWsTables;
+  if (own) {
+    e = hipMallocAsync((void**)&partial, (size_t)n_tables * nchunks * kKmax * sizeof(float), s);
+    if (e != hipSuccess) return e;
+  }
+  constexpr int kMaxY = 65535;  // tables per launch (grid y)
+  for (int t0 = 0; t0 < n_tables && e == hipSuccess; t0 += kMaxY) {
+    const int nt = std::min(n_tables - t0, kMaxY);
+    hipLaunchKernelGGL(amp_grad_partial, dim3((unsigned)nchunks, (unsigned)nt), dim3(256), 0, s, amp_part, mix_id,
+                       n, t0, nchunks, partial);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(amp_grad_finish, dim3((unsigned)n_tables), dim3(256), 0, s, partial, nchunks, grad_amp);
+    e = hipGetLastError();
+  }
+  if (own) {
+    const hipError_t e2 = hipFreeAsync(partial, s);
+    if (e == hipSuccess) e = e2;
+  }
+  return e;
+}
+
 extern "C" {
 
 size_t gfc_backward_workspace_bytes(int64_t n) {
-  return n > 0 ? (size_t)n * kKmax * sizeof(float) + 6 * sizeof(float) * (size_t)n : 0;
+  return n > 0 ? ((size_t)n * kKmax + 6 * (size_t)n + (size_t)kAgWsTables * amp_grad_chunks(n) * kKmax) * sizeof(float)
+               : 0;
 }
 
 gfc_status gfc_render_stamps_backward(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix* mix, const gfc_galaxies* gal,
@@ -493,11 +588,8 @@ gfc_status gfc_render_stamps_backward(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix*
     case 128: e = launch_bwd_small<128>(a, grad_out, gp, amp_part, s); break;
     case 256: e = launch_bwd_w256(a, grad_out, gp, amp_part, s); break;
   }
-  if (e == hipSuccess && grad_amp) {
-    hipLaunchKernelGGL(amp_grad_reduce, dim3(mix->n_tables * kKmax), dim3(256), 0, s, amp_part,
-                       gal->mix_id, n, grad_amp);
-    e = hipGetLastError();
-  }
+  if (e == hipSuccess && grad_amp)
+    e = launch_amp_grad(amp_part, gal->mix_id, n, mix->n_tables, grad_amp, ws + (size_t)n * (kKmax + 6), s);
   if (own) {
     hipError_t e2 = hipFreeAsync(ws, s);
     if (e == hipSuccess) e = e2;

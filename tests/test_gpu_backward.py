@@ -228,3 +228,55 @@ def test_autograd_function_matches_adjoint(ctx):
     assert torch.allclose(e1.grad, gp[:, 4]) and torch.allclose(e2.grad, gp[:, 5])
     assert torch.allclose(amp.grad, ga)
     psf.close(); mix.close()
+
+
+_PER_GALAXY = {}  # contributions from the first case, compared bit for bit by the others
+
+
+@pytest.mark.parametrize("n_tables", [1700, 70000, (1 << 20) // 14 + 1])
+def test_amplitude_sums_across_chunks_and_tables(ctx, n_tables):
+    """The per-table amplitude sums over 1,700 galaxies (14 chunks of 128 in
+    the two-pass reduction, the last one ragged).  Every table is a copy of
+    one mixture, so a call that gives each galaxy its own table returns each
+    galaxy's contribution exactly (one term per sum); a call with four shared
+    tables must then equal their float64 sums per table.  70,000 tables take
+    two launches of the first pass (at most 65,535 tables per grid row); with
+    74,899 the chunk partials would pass 64 MiB and the one-pass reduction
+    runs instead (its single-term sums must equal the others bit for bit)."""
+    import torch
+    import paper_2012_15797_amd as gfc
+
+    n, W = 1700, 16
+    rng = np.random.Generator(np.random.PCG64(700))  # the same galaxies in every case
+    cfg = wl.config_metric(10)
+    m = cfg["mix"].as_f32()
+    K = np.full(n_tables, int(m.K[0]), np.int32)
+    amp = np.broadcast_to(np.asarray(m.amp, np.float32)[:1], (n_tables, 16))
+    var = np.broadcast_to(np.asarray(m.var, np.float32)[:1], (n_tables, 16))
+    psf = gfc.Psf(ctx, cfg["psf"], cfg.get("psf_gauss"))
+    mix = gfc.Mixture(ctx, K, amp, var)
+    gal = wl.draw_galaxies(rng, n, W, 0)
+    g = torch.as_tensor(rng.standard_normal((n, W, W)).astype(np.float32)).cuda()
+
+    def amp_sums(mix_id):
+        _, ga = gfc.gfc_render_stamps_backward(ctx, psf, mix, gal.x, gal.y, gal.flux, gal.r_e, gal.e1, gal.e2,
+                                               W, g, mix_id=np.asarray(mix_id, np.int32))
+        torch.cuda.synchronize()
+        return ga.cpu().numpy()
+
+    own = np.arange(n) % n_tables
+    per_gal = amp_sums(own)[own].astype(np.float64)  # [n, 16], galaxy i's contribution
+    used = np.array(sorted({0, min(65535, n_tables - 1), n_tables // 3, n_tables - 1}))
+    shared = used[rng.integers(0, len(used), n)]
+    got = amp_sums(shared)
+    ref = np.zeros((n_tables, 16))
+    scale = np.zeros((n_tables, 16))
+    np.add.at(ref, shared, per_gal)
+    np.add.at(scale, shared, np.abs(per_gal))
+    err = np.abs(got - ref)
+    assert (err <= 1e-5 * scale).all(), float((err / np.maximum(scale, 1e-300)).max())
+    unused = np.setdiff1d(np.arange(n_tables), used)
+    assert (got[unused] == 0).all()
+    first = _PER_GALAXY.setdefault("per_gal", per_gal)
+    assert np.array_equal(per_gal, first)
+    psf.close(); mix.close()
