@@ -201,6 +201,10 @@ render_small_kernel(RenderArgs p) {
         const bool w4 = (int)threadIdx.x + 4 * C::BLOCK < NV;
         const float4* s0 = src + threadIdx.x;
         st0 = s0[0]; st1 = s0[C::BLOCK]; st2 = s0[2 * C::BLOCK]; st3 = s0[3 * C::BLOCK]; st4 = src[i4];
+        // the component weights, lane k evaluating component k's polynomial
+        // (J <= 16 lanes); the loop reads them back with a lane read
+        static_assert(C::WAVE1, "one stamp per wavefront");
+        const float ck = (l < p.eig_J) ? eigen_weight(p, l, up, vp) : 0.f;
         for (int j = 0; j < p.eig_J; ++j) {
           float4* dst = reinterpret_cast<float4*>(buf + (j & 1) * NS) + threadIdx.x;
           dst[0] = st0; dst[C::BLOCK] = st1; dst[2 * C::BLOCK] = st2; dst[3 * C::BLOCK] = st3;
@@ -211,7 +215,7 @@ render_small_kernel(RenderArgs p) {
             st0 = sj[threadIdx.x]; st1 = sj[threadIdx.x + C::BLOCK]; st2 = sj[threadIdx.x + 2 * C::BLOCK];
             st3 = sj[threadIdx.x + 3 * C::BLOCK]; st4 = sj[i4];
           }
-          const float cj = eigen_weight(p, j, up, vp);
+          const float cj = lane_f(ck, j);
           const float2* pj = buf + (j & 1) * NS;
           if (j == 0) {  // the first component initialises the sums (eig_J >= 1)
             static_for<0, M>([&](auto mm) {
