@@ -42,6 +42,11 @@ struct PerGalaxyTables {
 __global__ void __launch_bounds__(kPre) sersic_tables_kernel(const float* __restrict__ sersic_n, int S,
                                                              const float* __restrict__ grid, int K, int64_t n,
                                                              PerGalaxyTables t) {
+  // the grid indices staged in LDS once per block (S <= 256 = kPre), so the
+  // search below does not wait on one scalar load per index
+  __shared__ float s_grid[kPre];
+  if ((int)threadIdx.x < S) s_grid[threadIdx.x] = grid[threadIdx.x];
+  __syncthreads();
   const int64_t e = (int64_t)blockIdx.x * kPre + threadIdx.x;
   if (e >= n * kKmax) return;
   const int64_t g = e / kKmax;
@@ -49,11 +54,11 @@ __global__ void __launch_bounds__(kPre) sersic_tables_kernel(const float* __rest
   const float* amp = grid + S;
   const float* var = amp + S * K;
   const float nn = sersic_n[g];
-  const bool ok = __builtin_isfinite(nn) && nn >= grid[0] && nn <= grid[S - 1];
+  const bool ok = __builtin_isfinite(nn) && nn >= s_grid[0] && nn <= s_grid[S - 1];
   int s = 0;
   for (int i = 1; i < S - 1; ++i)
-    if (grid[i] <= nn) s = i;
-  const float t1 = ok ? (nn - grid[s]) / (grid[s + 1] - grid[s]) : 0.f, t0 = 1.f - t1;
+    if (s_grid[i] <= nn) s = i;
+  const float t1 = ok ? (nn - s_grid[s]) / (s_grid[s + 1] - s_grid[s]) : 0.f, t0 = 1.f - t1;
   float a = 0.f, v = 1.f;
   if (k < K) {
     a = fmaf(t0, amp[s * K + k], t1 * amp[(s + 1) * K + k]);
