@@ -17,7 +17,8 @@ the steps of Section 2 by hand:
   Section 2 step 3, differentiated through beta and theta (not through the
   trig-free closed form the GPU uses), so the two derivations are independent.
 
-Pinned by central finite differences of the forward oracle (tests).
+Pinned by central finite differences of the forward oracle (tests), also
+with a PSF Gaussian off the centre pixel and with a cross term.
 """
 
 from __future__ import annotations

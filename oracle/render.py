@@ -205,7 +205,9 @@ def real_space_image(x0, y0, coef, a, b, d, gauss, W: int) -> np.ndarray:
     coef_i * amp_p * N((c, r) - (x0, y0) - mu_p; C_i + Sigma_p), with
     N(u; S) = exp(-u^T S^-1 u / 2) / (2 pi sqrt(det S)), point-sampled at
     pixel centres.  Pinned by the closed-form Gaussian convolution and by
-    agreement with the Fourier path for large stamps (tests)."""
+    agreement with the Fourier path for large stamps, including a PSF whose
+    Gaussian is off the centre pixel and has a cross term, so the signs of
+    mu_p and of the covariance's cross term are fixed (tests)."""
     mux, muy, pxx, pxy, pyy, pamp = [float(v) for v in gauss]
     yy, xx = np.mgrid[0:W, 0:W].astype(np.float64)
     ux = xx - x0 - mux

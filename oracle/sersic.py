@@ -33,7 +33,10 @@ from .render import psf_spectrum, psf_gauss_moments, render_stamp
 
 
 def sersic_mixture(n_grid, amp, var, n: float):
-    """Reading S1: (A_k(n), v_k(n)), or None when n is off the grid (S2)."""
+    """Reading S1: (A_k(n), v_k(n)), or None when n is off the grid (S2).
+    Pinned by linearity in the amplitudes and, for the variances, by a
+    family whose nodes differ by a common variance factor, which must
+    render as the node stamp at a rescaled r_e (tests)."""
     n_grid = np.asarray(n_grid, np.float64)
     amp = np.asarray(amp, np.float64)
     var = np.asarray(var, np.float64)

@@ -64,3 +64,26 @@ def test_ramp_derivative_is_continuous():
         assert abs(lo - hi) < 1e-6 * abs(lo), (n_edge, lo, hi)
         lo, hi = (deriv(r_edge * math.exp(s), o.RAMP_LINEAR) for s in (-1e-9, 1e-9))
         assert abs(lo - hi) > 1e-3 * abs(lo), (n_edge, lo, hi)
+
+
+@pytest.mark.parametrize("W,flags,r_e", [(32, o.FORCE_REAL, 2.0), (32, 0, 3.0), (64, 0, 6.0)])
+def test_analytic_gradient_off_centre_elliptical_psf(W, flags, r_e):
+    """The real-space derivatives with a PSF Gaussian whose mean is off the
+    centre pixel and whose covariance has a cross term (step 8): the
+    Jacobian's image must equal the forward oracle's (pinned against the
+    Fourier route for this PSF) and its derivatives the central differences
+    of it, so a sign error in the mean or cross term fails here."""
+    P, gauss = wl.psf_offset_gaussian(64)
+    amp, var = wl.dev8_table(np.random.Generator(np.random.PCG64(11)))
+    ph = o.psf_spectrum(P, W)
+    p = dict(x=W / 2 + 0.31, y=W / 2 + 0.77, flux=7.0, r_e=r_e, e1=0.23, e2=-0.17)
+    g = np.random.Generator(np.random.PCG64(12)).standard_normal((W, W))
+    I, J = o.render_stamp_jacobian(ph, gauss, amp, var, W=W, flags=flags, **p)
+    np.testing.assert_allclose(I, o.render_stamp(ph, gauss, amp, var, W=W, flags=flags, **p),
+                               rtol=0, atol=1e-13 * np.abs(I).max())
+    an = o.loss_gradient(g, J)
+    fd = o.fd_gradient(ph, gauss, amp, var, p, W, g, flags=flags, h=1e-4)
+    scale = max(abs(an[k]) for k in PARAMS)
+    for k in PARAMS:
+        assert an[k] == pytest.approx(fd[k], rel=1e-6, abs=1e-8 * scale), k
+    np.testing.assert_allclose(an["amp"], fd["amp"], rtol=1e-6, atol=1e-8 * np.abs(an["amp"]).max())

@@ -233,3 +233,39 @@ def test_invalid_parameters_give_nan_stamp():
         p.update(bad)
         img = o.render_stamp(ph, g, [1.0], [1.0], W=16, **p)
         assert np.isnan(img).all()
+
+
+def test_real_space_route_off_centre_elliptical_psf():
+    """T10 with an off-centre, elliptical single-Gaussian PSF (mean
+    (0.37, -0.21) px from the centre pixel, covariance with a cross term).
+    The Fourier route sees the PSF only through its pixels (steps 1-2), the
+    real-space route only through the explicit description (step 8), so
+    their agreement pins the description's mean and cross term in step 8:
+    a sign error in either moves the real-space image by over 10% of the
+    peak.  Both also match the periodised analytic Gaussian centred at
+    x0 + mu_p with covariance C_i + Sigma_p."""
+    P, gauss = wl.psf_offset_gaussian(64)
+    amp, var = np.array([0.6, 0.4]), np.array([0.4, 1.2])
+    x0, y0, flux, r_e, e1, e2, W = 64.4, 63.7, 10.0, 3.0, 0.2, 0.35, 128
+    args = (amp, var, x0, y0, flux, r_e, e1, e2, W)
+    F = _render(P, gauss, *args, flags=o.FORCE_FOURIER)
+    R = _render(P, gauss, *args, flags=o.FORCE_REAL)
+    assert np.abs(F - R).max() / F.max() < 1e-8
+    a, b, d = o.covariances(r_e, e1, e2, var)
+    mux, muy, pxx, pxy, pyy, _ = gauss
+    ref = sum(flux * amp[i] * _periodized_gaussian(W, x0 + mux, y0 + muy, a[i] + pxx, b[i] + pxy,
+                                                   d[i] + pyy, images=1) for i in range(2))
+    assert np.abs(F - ref).max() / F.max() < 1e-8
+    # the hybrid route splits ramped components between the two; with a stamp
+    # small enough to ramp them the sum still matches the all-Fourier render of
+    # the same galaxy in a stamp large enough not to wrap
+    big = _render(P, gauss, amp, var, 64.4, 63.7, flux, 6.0, e1, e2, 128, o.FORCE_FOURIER)
+    hyb = _render(P, gauss, amp, var, 16.4, 15.7, flux, 6.0, e1, e2, 32)
+    parts = o.render_stamp(o.psf_spectrum(P, 32), gauss, amp, var, 16.4, 15.7, flux, 6.0, e1, e2, 32,
+                           return_parts=True)[1]
+    w = parts["w"]
+    assert np.any((w > 0) & (w < 1)) and np.any(w == 0), w        # one ramped, one real-space
+    fft32 = _render(P, gauss, amp, var, 16.4, 15.7, flux, 6.0, e1, e2, 32, o.FORCE_FOURIER)
+    e_hyb = np.abs(hyb - big[48:80, 48:80]).max() / big.max()
+    e_fft = np.abs(fft32 - big[48:80, 48:80]).max() / big.max()
+    assert e_hyb < 2e-4 and e_hyb < 0.02 * e_fft, (e_hyb, e_fft)

@@ -70,3 +70,28 @@ def test_composite_is_the_flux_weighted_sum(setup, f, rho):
     disk = o.render_stamp(S, g, ad, vd, x, y, F, re, e1, e2, W)
     bulge = o.render_stamp(S, g, ab, vb, x, y, F, rho * re, e1, e2, W)
     assert np.abs(got - ((1 - f) * disk + f * bulge)).max() <= 1e-12 * np.abs(got).max()
+
+
+@pytest.mark.parametrize("n,rho", [(0.8, 1.5), (2.25, 0.7), (3.9, 2.0), (5.99, 1.2)])
+def test_interpolated_variances_follow_an_r_e_rescaling(setup, n, rho):
+    """Variances, pinned by an independent route: a family whose node s+1
+    is node s with every variance times rho^2 and the same amplitudes.
+    Linear interpolation at t gives variances v_s (1 + t (rho^2 - 1)), and
+    since every covariance is v r_e^2 times a matrix of the ellipticity
+    (step 3), that stamp is the node-s stamp rendered at
+    r_e sqrt(1 + t (rho^2 - 1)).  Any other interpolation rule (geometric,
+    or of the standard deviations) renders a different size."""
+    S, g = setup
+    fam = wl.sersic_family()
+    grid = fam["n_grid"].astype(np.float64)
+    base_amp = fam["amp"][3].astype(np.float64)
+    base_var = fam["var"][3].astype(np.float64)
+    steps = np.arange(len(grid), dtype=np.float64)[:, None]
+    amp = np.repeat(base_amp[None], len(grid), axis=0)
+    var = base_var[None] * rho ** (2.0 * steps)
+    s = int(np.nonzero(grid <= n)[0][-1])
+    t = (n - grid[s]) / (grid[s + 1] - grid[s])
+    x, y, F, re, e1, e2, W = ARGS
+    got = osr.render_stamp_sersic(S, g, grid, amp, var, n, *ARGS)
+    ref = o.render_stamp(S, g, amp[s], var[s], x, y, F, re * np.sqrt(1.0 + t * (rho * rho - 1.0)), e1, e2, W)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()

@@ -21,6 +21,7 @@ from .generate import (  # noqa: F401
     psf_double_gaussian,
     psf_moffat_halo,
     psf_single_gaussian_fit,
+    psf_offset_gaussian,
     eigen_psf_moffat,
     draw_galaxies,
     config1,

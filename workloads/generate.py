@@ -138,6 +138,26 @@ def psf_moffat_halo(S: int = 64, fwhm: float = 4.5, beta: float = 3.0,
     return p / p.sum()
 
 
+OFFSET_PSF_MU = (0.37, -0.21)
+OFFSET_PSF_COV = ((3.1, 0.8), (0.8, 2.2))
+
+
+def psf_offset_gaussian(S: int = 64, mu=OFFSET_PSF_MU, cov=OFFSET_PSF_COV):
+    """One elliptical Gaussian N(mu, cov) sampled on S x S pixels, mu measured
+    from the centre pixel (S/2, S/2) and off it, cov with a cross term.
+    Returns (pixels normalised to unit sum, the explicit single-Gaussian
+    description {mu_x, mu_y, c_xx, c_xy, c_yy, amp = 1}).  At these widths the
+    sampled grid's moments equal (mu, cov) to ~1e-15, so the description is
+    exact for the pixel PSF: a test PSF for the real-space route's mean and
+    cross term, which centred isotropic PSFs leave untested."""
+    X, Y = _grid(S)
+    (cxx, cxy), (_, cyy) = cov
+    det = cxx * cyy - cxy * cxy
+    ux, uy = X - mu[0], Y - mu[1]
+    p = np.exp(-0.5 * (cyy * ux * ux - 2.0 * cxy * ux * uy + cxx * uy * uy) / det)
+    return p / p.sum(), np.array([mu[0], mu[1], cxx, cxy, cyy, 1.0])
+
+
 def eigen_psf_moffat(S: int = 64, degree: int = 2, image_size: float = 4096.0, n_fit: int = 7):
     """Synthetic spatially varying PSF in eigen form (components with
     polynomial amplitudes, as PSF-modelling tools produce them).  The true
