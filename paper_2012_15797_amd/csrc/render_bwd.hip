@@ -87,19 +87,21 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
   const float trB = G.b11 + G.b22;
   const int kloop = (C::SPB == 1) ? G.K : p.kmax;
 
-  // per-component constants of the Fourier sums, computed once per stamp
+  // per-component constants of the Fourier sums, computed once per stamp:
+  // v, w A, w A v and w (w = 0 past the table's K).  A component with A = 0
+  // still needs its sums: dL/dA does not depend on A.
   if (l < kKmax) {
     const float v = var[l];
-    const float A = (l < G.K) ? amp[l] : 0.f;
-    const float wa = route_weight<W>(v * trB, p.flags) * A;
-    s_cmp[slot][l] = make_float4(v, wa, wa * v, 0.f);
+    const bool in = l < G.K;
+    const float w = in ? route_weight<W>(v * trB, p.flags) : 0.f;
+    const float wa = w * (in ? amp[l] : 0.f);
+    s_cmp[slot][l] = make_float4(v, wa, wa * v, w);
   }
 
-  // routing: components with a real-space share
+  // routing: components with a real-space share (whatever their amplitude)
   unsigned rmask = 0;
   for (int k = 0; k < kloop; ++k) {
-    const float A = (k < G.K) ? amp[k] : 0.f;
-    if (A != 0.f && route_weight<W>(var[k] * trB, p.flags) < 1.f) rmask |= 1u << k;
+    if (k < G.K && route_weight<W>(var[k] * trB, p.flags) < 1.f) rmask |= 1u << k;
   }
 
   // ------------------------------------------------------------ load + real space
@@ -346,7 +348,7 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
       // where the ramp slope vanishes too
       const float4 cp = s_cmp[slot][k];
       const float v = cp.x, wa = cp.y, wav = cp.z;
-      if (wa == 0.f) continue;
+      if (cp.w == 0.f) continue;
       float pk = 0.f;
       static_for<0, nb>([&](auto jj) {
         constexpr int j = decltype(jj)::value;

@@ -73,7 +73,7 @@ render_bwd_w256_kernel(RenderArgs p, const float* __restrict__ gout, float* __re
 
   unsigned rmask = 0;
   for (int k = 0; k < G.K; ++k)
-    if (amp[k] != 0.f && route_weight<W>(var[k] * trB, p.flags) < 1.f) rmask |= 1u << k;
+    if (route_weight<W>(var[k] * trB, p.flags) < 1.f) rmask |= 1u << k;  // whatever A_k (dL/dA_k needs it)
   if (l < kKmax * 6) (&s_racc[0][0])[l] = 0.f;
 
   // ------------------------------------------------------------ load + real space
@@ -344,8 +344,9 @@ render_bwd_w256_kernel(RenderArgs p, const float* __restrict__ gout, float* __re
     });
     for (int k = 0; k < G.K; ++k) {
       const float v = var[k];
-      const float wa = route_weight<W>(v * trB, p.flags) * amp[k];
-      if (wa == 0.f) continue;
+      const float w = route_weight<W>(v * trB, p.flags);
+      if (w == 0.f) continue;  // A_k = 0 still needs p_k for dL/dA_k
+      const float wa = w * amp[k];
       const float wav = wa * v;
       float pk = 0.f;
       static_for<0, nb>([&](auto jj) {

@@ -468,8 +468,9 @@ render_small_kernel(RenderArgs p) {
       // columns are filtered along y in registers as the tile's rows are
       // read.  Taps outside the stamp have weight zero.
       if (rmask != 0) {
-        // Real-space components along this lane's row: e(x) is a quadratic in
-        // the column x with per-row coefficients, two FMAs per pixel.
+        // Real-space components along this lane's row: the exponent is a
+        // quadratic in the column x with per-row coefficients, two FMAs per
+        // pixel.
         const float dy = (float)y + dyc;
         const float dx0 = -G.x0 - pg[0];  // dx of column 0
         for (unsigned mk = rmask; mk != 0; mk &= mk - 1) {
@@ -481,19 +482,20 @@ render_small_kernel(RenderArgs p) {
           const float det = fmaf(sxx, syy, -(sxy * sxy));
           const float rdet = __builtin_amdgcn_rcpf(det);
           const float ampr = ra * G.flux * pg[5] * kInv2Pi * __builtin_amdgcn_rsqf(det);
-          const float c0 = kHalfLog2e * (syy * rdet);
-          const float c1 = -2.f * kHalfLog2e * (sxy * rdet);
-          const float a2 = kHalfLog2e * (sxx * rdet);
-          // e = c0 dx^2 + c1 dx dy + a2 dy^2 with dx = x + dx0
-          const float q2 = c0;
-          const float q1 = fmaf(2.f * c0, dx0, c1 * dy);
-          const float q0 = fmaf(dx0, fmaf(c0, dx0, c1 * dy), a2 * dy * dy);
+          // Along this lane's row (dy fixed) the quadratic form is
+          // dy^2 / syy + (syy / det) (dx - (sxy / syy) dy)^2, completed about
+          // the conditional mean so that no large terms cancel near the peak:
+          // with dx = x + dx0 the exponent is k - u^2, u = g (x + m).
+          const float rsyy = __builtin_amdgcn_rcpf(syy);
+          const float g = sqrtf(-kHalfLog2e * syy * rdet);
+          const float k0 = kHalfLog2e * dy * dy * rsyy;
+          const float gm = g * fmaf(-sxy * rsyy, dy, dx0);
           static_for<0, W / 2>([&](auto xx) {
             constexpr int x = 2 * decltype(xx)::value;  // two columns at a time
-            const float e0 = fmaf((float)x, fmaf(q2, (float)x, q1), q0);
-            const float e1 = fmaf((float)(x + 1), fmaf(q2, (float)(x + 1), q1), q0);
-            R[x >> 1].x = fmaf(ampr, __builtin_amdgcn_exp2f(e0), R[x >> 1].x);
-            R[x >> 1].y = fmaf(ampr, __builtin_amdgcn_exp2f(e1), R[x >> 1].y);
+            const float u0 = fmaf(g, (float)x, gm);
+            const float u1 = fmaf(g, (float)(x + 1), gm);
+            R[x >> 1].x = fmaf(ampr, __builtin_amdgcn_exp2f(fmaf(-u0, u0, k0)), R[x >> 1].x);
+            R[x >> 1].y = fmaf(ampr, __builtin_amdgcn_exp2f(fmaf(-u1, u1, k0)), R[x >> 1].y);
           });
         }
       }
@@ -576,22 +578,26 @@ render_small_kernel(RenderArgs p) {
           const float det = fmaf(sxx, syy, -(sxy * sxy));
           const float rdet = __builtin_amdgcn_rcpf(det);
           const float ampr = ra * G.flux * pg[5] * kInv2Pi * __builtin_amdgcn_rsqf(det);
-          const float a0 = kHalfLog2e * (syy * rdet) * dx * dx;
-          const float a1 = -2.f * kHalfLog2e * (sxy * rdet) * dx;
-          const float a2 = kHalfLog2e * (sxx * rdet);
-          // e = a0 + dy (a1 + a2 dy) with dy = dyq + r, as a quadratic in the
-          // tile row r: e0 + r (e1 + a2 r), two FMAs with an immediate r
+          // Along this lane's column (dx fixed) the quadratic form is
+          // dx^2 / sxx + (sxx / det) (dy - (sxy / sxx) dx)^2: the square is
+          // completed about the conditional mean, so the exponent stays a
+          // difference of small terms near the peak whatever the tile row
+          // (an expansion about the tile's first row cancels terms of size
+          // (W/2)^2 / syy there).  With dy = dyq + r the exponent is
+          // k - u^2, u = g (r + m): two FMAs with an immediate r.
+          const float rsxx = __builtin_amdgcn_rcpf(sxx);
+          const float g = sqrtf(-kHalfLog2e * sxx * rdet);
+          const float k0 = kHalfLog2e * dx * dx * rsxx;
           const float dyq = (float)(q * C::HR) + dyc;
-          const float e0 = fmaf(dyq, fmaf(a2, dyq, a1), a0);
-          const float e1 = fmaf(2.f * a2, dyq, a1);
+          const float gm = g * fmaf(-sxy * rsxx, dx, dyq);
           // two rows at a time, so that each exponential has an independent
           // instruction between it and its use
           static_for<0, C::HR / 2>([&](auto rr) {
             constexpr int r = 2 * decltype(rr)::value;
-            const float x0 = (r == 0) ? e0 : fmaf((float)r, fmaf(a2, (float)r, e1), e0);
-            const float x1 = fmaf((float)(r + 1), fmaf(a2, (float)(r + 1), e1), e0);
-            val[r] = fmaf(ampr, __builtin_amdgcn_exp2f(x0), val[r]);
-            val[r + 1] = fmaf(ampr, __builtin_amdgcn_exp2f(x1), val[r + 1]);
+            const float u0 = fmaf(g, (float)r, gm);
+            const float u1 = fmaf(g, (float)(r + 1), gm);
+            val[r] = fmaf(ampr, __builtin_amdgcn_exp2f(fmaf(-u0, u0, k0)), val[r]);
+            val[r + 1] = fmaf(ampr, __builtin_amdgcn_exp2f(fmaf(-u1, u1, k0)), val[r + 1]);
           });
         }
       }

@@ -402,20 +402,22 @@ render_large_kernel(RenderArgs p, float2* __restrict__ scratch) {
             const float det = fmaf(sxx, syy, -(sxy * sxy));
             const float rdet = __builtin_amdgcn_rcpf(det);
             const float ampr = ra * G.flux * pg[5] * kInv2Pi * __builtin_amdgcn_rsqf(det);
-            const float a0 = kHalfLog2e * (syy * rdet) * dx * dx;
-            const float a1 = -2.f * kHalfLog2e * (sxy * rdet) * dx;
-            const float a2 = kHalfLog2e * (sxx * rdet);
-            // output row srow0 + r: the exponent a0 + dy (a1 + a2 dy) as a
-            // quadratic in r, two FMAs with an immediate per pixel
+            // output row srow0 + r: along the column the quadratic form is
+            // dx^2 / sxx + (sxx / det) (dy - (sxy / sxx) dx)^2, completed about
+            // the conditional mean (no large terms cancel near the peak); the
+            // exponent is k - u^2 with u = g (r + m), two FMAs with an
+            // immediate per pixel
+            const float rsxx = __builtin_amdgcn_rcpf(sxx);
+            const float g = sqrtf(-kHalfLog2e * sxx * rdet);
+            const float k0 = kHalfLog2e * dx * dx * rsxx;
             const float dyq = (float)srow0 - G.y0 - pg[1];
-            const float e0 = fmaf(dyq, fmaf(a2, dyq, a1), a0);
-            const float e1 = fmaf(2.f * a2, dyq, a1);
+            const float gm = g * fmaf(-sxy * rsxx, dx, dyq);
             static_for<0, RPL / 2>([&](auto rq) {
               constexpr int r = 2 * decltype(rq)::value;
-              const float x0 = (r == 0) ? e0 : fmaf((float)r, fmaf(a2, (float)r, e1), e0);
-              const float x1 = fmaf((float)(r + 1), fmaf(a2, (float)(r + 1), e1), e0);
-              val[r] = fmaf(ampr, __builtin_amdgcn_exp2f(x0), val[r]);
-              val[r + 1] = fmaf(ampr, __builtin_amdgcn_exp2f(x1), val[r + 1]);
+              const float u0 = fmaf(g, (float)r, gm);
+              const float u1 = fmaf(g, (float)(r + 1), gm);
+              val[r] = fmaf(ampr, __builtin_amdgcn_exp2f(fmaf(-u0, u0, k0)), val[r]);
+              val[r + 1] = fmaf(ampr, __builtin_amdgcn_exp2f(fmaf(-u1, u1, k0)), val[r + 1]);
             });
           }
           static_for<0, RPL>([&](auto rq) {

@@ -2,10 +2,11 @@
 against the FP64 derivative oracle, which itself is pinned to central finite
 differences on the CPU (tests/test_oracle_grad.py).
 
-Bar: for each parameter, |gpu - oracle| <= 1e-4 |oracle| + 1e-5 rms(oracle),
-where rms is over the galaxies of the case (the second term covers gradients
-that cancel to nearly zero, whose float32 rounding is set by the size of the
-summed terms, not by the result)."""
+Bar: for each parameter, |gpu - oracle| <= 1e-4 |oracle| wherever |oracle| is
+at least 1e-2 of its rms over the case's galaxies; below that 1e-5 rms is
+added (gradients that cancel to nearly zero, or galaxies far fainter than the
+case's brightest, whose float32 rounding is set by the size of the summed
+terms, not by the result)."""
 
 import math
 
@@ -14,66 +15,15 @@ import pytest
 
 import oracle as o
 import workloads as wl
-from gpu_helpers import lib_objects
+from gpu_helpers import assert_grads_close as assert_close, gpu_grads, lib_objects, oracle_grads
 from oracle.grad import PARAMS
 
 pytestmark = pytest.mark.gpu
-
-RTOL, ATOL_RMS = 1e-4, 1e-5
-
 
 @pytest.fixture(scope="module")
 def ctx():
     import paper_2012_15797_amd as gfc
     return gfc.Context.default(0)
-
-
-def oracle_grads(cfg, gal, g, flags=0, cd=None):
-    """Per-galaxy dL/d(x, y, flux, log r_e, e1, e2) and per-table amplitude
-    sums from the FP64 analytic Jacobian, with the float32 inputs the GPU saw."""
-    mix = cfg["mix"].as_f32()
-    P = np.asarray(cfg["psf"], np.float32).astype(np.float64)
-    gauss = cfg.get("psf_gauss")
-    gauss = o.psf_gauss_moments(P) if gauss is None else gauss
-    cache = {}
-    gp = np.zeros((len(gal), 6))
-    ga = np.zeros((mix.n_tables, 16))
-    for i in range(len(gal)):
-        p = gal.params(i)
-        W = p["W"]
-        if W not in cache:
-            cache[W] = o.psf_spectrum(P, W)
-        amp, var = mix.table(p["mix_id"])
-        _, J = o.render_stamp_jacobian(cache[W], gauss, amp, var, p["x"], p["y"], p["flux"], p["r_e"],
-                                       p["e1"], p["e2"], W, flags, cd)
-        lg = o.loss_gradient(np.asarray(g[i], np.float64), J)
-        gp[i] = [lg[k] for k in PARAMS]
-        ga[p["mix_id"], : len(amp)] += lg["amp"]
-    return gp, ga
-
-
-def gpu_grads(ctx, psf, mix, gal, W, g, flags=0, cd=None):
-    import torch
-    import paper_2012_15797_amd as gfc
-
-    gt = torch.as_tensor(np.ascontiguousarray(g, np.float32)).cuda()
-    gp, ga = gfc.gfc_render_stamps_backward(ctx, psf, mix, gal.x, gal.y, gal.flux, gal.r_e, gal.e1,
-                                            gal.e2, W, gt, mix_id=gal.mix_id, flags=flags, cd=cd)
-    torch.cuda.synchronize()
-    return gp.cpu().numpy().astype(np.float64), ga.cpu().numpy().astype(np.float64)
-
-
-def assert_close(gpu, ref, what):
-    ref = np.asarray(ref, np.float64)
-    rms = np.sqrt(np.mean(ref**2, axis=0, keepdims=True))
-    bound = np.broadcast_to(RTOL * np.abs(ref) + ATOL_RMS * rms, ref.shape)
-    err = np.abs(gpu - ref)
-    bad = err > bound
-    if bad.any():
-        i = tuple(np.argwhere(bad)[0])
-        worst = float((err / np.maximum(bound, 1e-300)).max())
-        raise AssertionError(f"{what}: {int(bad.sum())} of {bad.size} out of tolerance (worst {worst:.2f}x "
-                             f"the bound); first {i}: gpu {gpu[i]:.6e} oracle {ref[i]:.6e} bound {bound[i]:.3e}")
 
 
 @pytest.mark.parametrize("W", [16, 32, 64, 128, 256])
@@ -85,9 +35,9 @@ def test_backward_each_size(ctx, W):
     g = rng.standard_normal((n, W, W)).astype(np.float32)
     psf, mix = lib_objects(ctx, cfg)
     gp, ga = gpu_grads(ctx, psf, mix, gal, W, g)
-    rp, ra = oracle_grads(cfg, gal, g)
+    rp, ra, ra_abs = oracle_grads(cfg, gal, g)
     assert_close(gp, rp, f"params W={W}")
-    assert_close(ga, ra, f"amplitudes W={W}")
+    assert_close(ga, ra, f"amplitudes W={W}", scale=ra_abs)
     psf.close(); mix.close()
 
 
@@ -104,7 +54,7 @@ def test_backward_w256_across_chunks(ctx):
     gp, _ = gpu_grads(ctx, psf, mix, gal, W, g)
     assert np.isfinite(gp).all()
     idx = [0, 1, 1022, 1023, 1024, 1025, 1029]
-    rp, _ = oracle_grads(cfg, gal.subset(idx), g[idx])
+    rp, _, _ = oracle_grads(cfg, gal.subset(idx), g[idx])
     assert_close(gp[idx], rp, "params W=256 chunk boundary")
     psf.close(); mix.close()
 
@@ -118,9 +68,9 @@ def test_backward_routing_flags(ctx, flags):
     g = rng.standard_normal((n, W, W)).astype(np.float32)
     psf, mix = lib_objects(ctx, cfg)
     gp, ga = gpu_grads(ctx, psf, mix, gal, W, g, flags=flags)
-    rp, ra = oracle_grads(cfg, gal, g, flags=flags)
+    rp, ra, ra_abs = oracle_grads(cfg, gal, g, flags=flags)
     assert_close(gp, rp, f"params flags={flags}")
-    assert_close(ga, ra, f"amplitudes flags={flags}")
+    assert_close(ga, ra, f"amplitudes flags={flags}", scale=ra_abs)
     psf.close(); mix.close()
 
 
@@ -136,9 +86,9 @@ def test_backward_forced_real_each_size(ctx, W):
     g = rng.standard_normal((n, W, W)).astype(np.float32)
     psf, mix = lib_objects(ctx, cfg)
     gp, ga = gpu_grads(ctx, psf, mix, gal, W, g, flags=2)
-    rp, ra = oracle_grads(cfg, gal, g, flags=2)
+    rp, ra, ra_abs = oracle_grads(cfg, gal, g, flags=2)
     assert_close(gp, rp, f"params W={W} forced real")
-    assert_close(ga, ra, f"amplitudes W={W} forced real")
+    assert_close(ga, ra, f"amplitudes W={W} forced real", scale=ra_abs)
     psf.close(); mix.close()
 
 
@@ -157,9 +107,9 @@ def test_backward_fit_workload(ctx):
     g = ((I - T) / sigma**2).astype(np.float32)
     psf, mix = lib_objects(ctx, cfg)
     gp, ga = gpu_grads(ctx, psf, mix, gal, 64, g)
-    rp, ra = oracle_grads(cfg, gal, g)
+    rp, ra, ra_abs = oracle_grads(cfg, gal, g)
     assert_close(gp, rp, "params fit workload")
-    assert_close(ga, ra, "amplitudes fit workload")
+    assert_close(ga, ra, "amplitudes fit workload", scale=ra_abs)
     psf.close(); mix.close()
 
 
@@ -172,9 +122,9 @@ def test_backward_cd_matrix(ctx):
     cd = np.array([0.9, 0.15, -0.2, 1.1], np.float32)
     psf, mix = lib_objects(ctx, cfg)
     gp, ga = gpu_grads(ctx, psf, mix, gal, W, g, cd=cd)
-    rp, ra = oracle_grads(cfg, gal, g, cd=cd.astype(np.float64))
+    rp, ra, ra_abs = oracle_grads(cfg, gal, g, cd=cd.astype(np.float64))
     assert_close(gp, rp, "params cd")
-    assert_close(ga, ra, "amplitudes cd")
+    assert_close(ga, ra, "amplitudes cd", scale=ra_abs)
     psf.close(); mix.close()
 
 
