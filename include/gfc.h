@@ -248,6 +248,26 @@ gfc_status gfc_render_stamps_backward(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix*
                                       float* grad_params, float* grad_amp,
                                       void* workspace, void* hip_stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight fit loops, harnesses that forbid hipMalloc.  The adjoint of
+ * gfc_render_stamps_backward with the same arguments (workspace aside) and
+ * the same results, bit for bit, but its scratch (amplitude partials,
+ * parameter gradients for a NULL grad_params, the per-table partial sums)
+ * is a fixed array inside the library, one per device (24 MiB, taken when
+ * the first context on that device is created and held until the process
+ * ends).  It allocates and frees nothing.  Limits, each GFC_EINVAL: W <= 128,
+ * n <= GFC_NOALLOC_MAX_GALAXIES, and the PSF spectrum for W already cached
+ * (gfc_psf_prepare).  More than 16 tables are summed in one pass over the
+ * galaxies, without partials.  Every call on a device uses that device's one
+ * array: calls that overlap on one device (two streams, or two threads)
+ * race and give wrong gradients, so the caller serialises them. */
+#define GFC_NOALLOC_MAX_GALAXIES 262144
+gfc_status gfc_render_stamps_backward_noalloc(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix* mix,
+                                              const gfc_galaxies* gal, int64_t n, int W,
+                                              unsigned flags, const float* grad_out,
+                                              float* grad_params, float* grad_amp,
+                                              void* hip_stream);
+
 /* -------------------------------------------------------------- serving */
 /* Continuous batching.  A request carries HOST parameter arrays (copied at
  * submit).  Its output stamps live in a library-owned device buffer, charged

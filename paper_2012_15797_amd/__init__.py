@@ -12,6 +12,7 @@ from ._lib import (  # noqa: F401
     GFC_FORCE_FOURIER,
     GFC_FORCE_REAL,
     GFC_KMAX,
+    GFC_NOALLOC_MAX_GALAXIES,
     GFC_RAMP_LINEAR,
     GFC_SHIFT_LANCZOS3,
     GfcError,
@@ -26,6 +27,7 @@ from .api import (  # noqa: F401
     gfc_backward_workspace_bytes,
     gfc_render_stamps,
     gfc_render_stamps_backward,
+    gfc_render_stamps_backward_noalloc,
     gfc_render_stamps_composite,
     gfc_render_stamps_sersic,
 )

@@ -21,6 +21,7 @@ GFC_FORCE_REAL = 2
 GFC_RAMP_LINEAR = 4
 GFC_SHIFT_LANCZOS3 = 8
 GFC_ACCUMULATE = 16
+GFC_NOALLOC_MAX_GALAXIES = 262144
 
 STATUS = {
     0: "GFC_OK", -1: "GFC_EINVAL", -2: "GFC_EUNSUPPORTED", -3: "GFC_ENOMEM",
@@ -89,6 +90,8 @@ PROTOTYPES = {
     "gfc_backward_workspace_bytes": (ctypes.c_size_t, [I64]),
     "gfc_render_stamps_backward": (I32, [P, P, P, ctypes.POINTER(gfc_galaxies), I64, I32, U32,
                                          P, P, P, P, P]),
+    "gfc_render_stamps_backward_noalloc": (I32, [P, P, P, ctypes.POINTER(gfc_galaxies), I64, I32, U32,
+                                                 P, P, P, P]),
     "gfc_server_create": (I32, [P, ctypes.c_size_t, I32, I64, PP]),
     "gfc_server_submit": (I32, [P, ctypes.POINTER(gfc_request), ctypes.POINTER(U64)]),
     "gfc_server_poll": (I32, [P, U64, ctypes.POINTER(I32), PP, ctypes.POINTER(I32)]),

@@ -309,3 +309,27 @@ def gfc_render_stamps_backward(ctx, psf, mix, x, y, flux, r_e, e1, e2, W, grad_o
          ctypes.c_void_p(grad_amp.data_ptr()), ws, _stream_ptr(ctx.device))
     del keep
     return grad_params, grad_amp
+
+
+def gfc_render_stamps_backward_noalloc(ctx, psf, mix, x, y, flux, r_e, e1, e2, W, grad_out, mix_id=None,
+                                       flags=0, cd=None, grad_params=None, grad_amp=None):
+    """Allocation-free adjoint (gfc_render_stamps_backward_noalloc): the
+    library's scratch is a fixed per-device array, so the C call allocates
+    nothing (W <= 128, n <= GFC_NOALLOC_MAX_GALAXIES, the PSF spectrum for W
+    prepared beforehand).  Output tensors are allocated here by torch unless
+    the caller passes them.  Returns (grad_params [n, 6], grad_amp
+    [n_tables, 16] accumulated)."""
+    dev = ctx.torch_device
+    g, n, keep = _galaxies(dev, x, y, flux, r_e, e1, e2, mix_id, cd)
+    go = grad_out.to(dev, torch.float32).contiguous()
+    if go.numel() != n * W * W:
+        raise ValueError("grad_out must hold n*W*W elements")
+    if grad_params is None:
+        grad_params = torch.empty((n, 6), dtype=torch.float32, device=dev)
+    if grad_amp is None:
+        grad_amp = torch.zeros((mix.n_tables, GFC_KMAX), dtype=torch.float32, device=dev)
+    call("gfc_render_stamps_backward_noalloc", ctx.handle, psf.handle, mix.handle, ctypes.byref(g), int(n),
+         int(W), int(flags), ctypes.c_void_p(go.data_ptr()), ctypes.c_void_p(grad_params.data_ptr()),
+         ctypes.c_void_p(grad_amp.data_ptr()), _stream_ptr(ctx.device))
+    del keep
+    return grad_params, grad_amp

@@ -81,6 +81,12 @@ gfc_status psf_cache(gfc_psf* psf, int W, hipStream_t stream, const PsfSpectrum*
   return GFC_OK;
 }
 
+const PsfSpectrum* psf_cache_find(gfc_psf* psf, int W) {
+  std::lock_guard<std::mutex> lock(psf->mu);
+  const auto it = psf->cache.find(W);
+  return it == psf->cache.end() ? nullptr : &it->second;
+}
+
 gfc_status fill_render_args(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix* mix, const gfc_galaxies* gal,
                             int64_t n, int W, unsigned flags, RenderArgs* a) {
   if (!ctx || !psf || !mix || !gal) return fail(GFC_EINVAL, "null handle or galaxy block");
@@ -184,6 +190,8 @@ gfc_status gfc_ctx_create(int hip_device, gfc_ctx** out) {
   if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(GFC_EUNSUPPORTED, std::string("this library is built for gfx950, device is ") + prop.gcnArchName);
+  const gfc_status st = noalloc_scratch_setup(hip_device);
+  if (st != GFC_OK) return st;
   auto* ctx = new (std::nothrow) gfc_ctx();
   if (!ctx) return fail(GFC_ENOMEM, "context allocation failed");
   ctx->device = hip_device;

@@ -71,6 +71,11 @@ class DeviceGuard {
 };
 
 gfc_status psf_cache(gfc_psf* psf, int W, hipStream_t stream, const PsfSpectrum** out);
+// The cached spectrum for W, or nullptr when it has not been filled (never fills).
+const PsfSpectrum* psf_cache_find(gfc_psf* psf, int W);
+// Takes the device address of the allocation-free adjoint's scratch array on
+// `device` (current); once per device, from gfc_ctx_create.
+gfc_status noalloc_scratch_setup(int device);
 gfc_status fill_render_args(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix* mix, const gfc_galaxies* gal,
                             int64_t n, int W, unsigned flags, RenderArgs* a);
 // Points the render arguments at a cached spectrum.

@@ -20,6 +20,9 @@
 //  column DFT  lane (c, h): decimation in frequency, rows k_y = 2m + h
 //  bins        exponentials per component, accumulations, lane reductions
 //  chain rule  B -> (log r_e, e1, e2) and the routing weights, one lane.
+#include <map>
+#include <mutex>
+
 #include "gfc_device.hpp"
 #include "gfc_internal.hpp"
 #include "gfc_launch.hpp"
@@ -515,11 +518,13 @@ constexpr int kAgWsTables = 16;
 
 static int64_t amp_grad_chunks(int64_t n) { return (n + kAgChunk - 1) / kAgChunk; }
 
-// ws_partial: the workspace's room for kAgWsTables tables' partials.
+// ws_partial: the workspace's room for kAgWsTables tables' partials.  With
+// more tables the partials take a stream-ordered allocation, unless
+// may_allocate is false: then the one-pass reduction runs instead.
 static hipError_t launch_amp_grad(const float* amp_part, const int32_t* mix_id, int64_t n, int n_tables,
-                                  float* grad_amp, float* ws_partial, hipStream_t s) {
+                                  float* grad_amp, float* ws_partial, hipStream_t s, bool may_allocate = true) {
   const int64_t nchunks = amp_grad_chunks(n);
-  if ((int64_t)n_tables * nchunks > (int64_t)1 << 20) {
+  if ((int64_t)n_tables * nchunks > (int64_t)1 << 20 || (n_tables > kAgWsTables && !may_allocate)) {
     hipLaunchKernelGGL(amp_grad_reduce, dim3(n_tables * kKmax), dim3(256), 0, s, amp_part, mix_id, n, grad_amp);
     return hipGetLastError();
   }
@@ -546,6 +551,46 @@ static hipError_t launch_amp_grad(const float* amp_part, const int32_t* mix_id, 
     if (e == hipSuccess) e = e2;
   }
   return e;
+}
+
+// ---------------------------------------------------------------- allocation-free adjoint
+// Scratch of gfc_render_stamps_backward_noalloc, laid out as the workspace of
+// gfc_render_stamps_backward for n galaxies: amplitude partials [n][kKmax],
+// parameter gradients [n][6] (used when grad_params is NULL), then the
+// two-pass reduction's partials for kAgWsTables tables.  Sized for
+// GFC_NOALLOC_MAX_GALAXIES; each device holds its own copy (24 MiB) from
+// the first context created on it until the process ends.  Every call on a
+// device shares that copy, and each call overwrites what it reads, so
+// nothing needs clearing between calls.
+constexpr int64_t kNoAllocMax = GFC_NOALLOC_MAX_GALAXIES;
+constexpr size_t kNoAllocFloats =
+    (size_t)kNoAllocMax * (kKmax + 6) + (size_t)kAgWsTables * ((kNoAllocMax + kAgChunk - 1) / kAgChunk) * kKmax;
+static __device__ __align__(256) float scratch[kNoAllocFloats];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, float*> g_scratch_ptr;  // HIP device -> address of that device's `scratch`
+}  // namespace
+
+namespace gfc {
+// Takes the device address of `scratch` on `device`, which must be current.
+// Host code uses only this address: the array's name is a host-side stand-in.
+gfc_status noalloc_scratch_setup(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr.count(device)) return GFC_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress of the adjoint's scratch array");
+  if (!ptr) return fail(GFC_EDEVICE, "the adjoint's scratch array has no device address");
+  g_scratch_ptr[device] = static_cast<float*>(ptr);
+  return GFC_OK;
+}
+}  // namespace gfc
+
+static float* noalloc_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  const auto it = g_scratch_ptr.find(device);
+  return it == g_scratch_ptr.end() ? nullptr : it->second;
 }
 
 extern "C" {
@@ -596,6 +641,44 @@ gfc_status gfc_render_stamps_backward(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix*
     hipError_t e2 = hipFreeAsync(ws, s);
     if (e == hipSuccess) e = e2;
   }
+  if (e != hipSuccess) return hip_fail(e, "backward launch");
+  return GFC_OK;
+}
+
+gfc_status gfc_render_stamps_backward_noalloc(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix* mix,
+                                              const gfc_galaxies* gal, int64_t n, int W, unsigned flags,
+                                              const float* grad_out, float* grad_params, float* grad_amp,
+                                              void* hip_stream) {
+  if (psf && psf->J > 0) return fail(GFC_EUNSUPPORTED, "the adjoint takes a constant PSF");
+  if (flags & GFC_SHIFT_LANCZOS3) return fail(GFC_EUNSUPPORTED, "the adjoint uses the Fourier-phase shift");
+  if (flags & GFC_ACCUMULATE) return fail(GFC_EINVAL, "GFC_ACCUMULATE applies to forward renders");
+  RenderArgs a;
+  gfc_status st = fill_render_args(ctx, psf, mix, gal, n, W, flags, &a);
+  if (st != GFC_OK) return st;
+  if (W > 128) return fail(GFC_EINVAL, "the allocation-free adjoint takes stamp sizes up to 128");
+  if (n > kNoAllocMax)
+    return fail(GFC_EINVAL, "the allocation-free adjoint takes at most GFC_NOALLOC_MAX_GALAXIES galaxies per call");
+  if (n == 0) return GFC_OK;
+  if (!grad_out) return fail(GFC_EINVAL, "null upstream gradient");
+  DeviceGuard guard(ctx->device);
+  const PsfSpectrum* spec = psf_cache_find(psf, W);
+  if (!spec) return fail(GFC_EINVAL, "no cached PSF spectrum for this stamp size: call gfc_psf_prepare first");
+  attach_spectrum(&a, spec);
+  float* ws = noalloc_scratch(ctx->device);
+  if (!ws) return fail(GFC_EDEVICE, "the adjoint's scratch array is not set up on this device");
+  hipStream_t s = (hipStream_t)hip_stream;
+  float* amp_part = ws;
+  float* gp = grad_params ? grad_params : ws + (size_t)n * kKmax;
+  hipError_t e = hipSuccess;
+  switch (W) {
+    case 16: e = launch_bwd_small<16>(a, grad_out, gp, amp_part, s); break;
+    case 32: e = launch_bwd_small<32>(a, grad_out, gp, amp_part, s); break;
+    case 64: e = launch_bwd_small<64>(a, grad_out, gp, amp_part, s); break;
+    case 128: e = launch_bwd_small<128>(a, grad_out, gp, amp_part, s); break;
+  }
+  if (e == hipSuccess && grad_amp)
+    e = launch_amp_grad(amp_part, gal->mix_id, n, mix->n_tables, grad_amp, ws + (size_t)n * (kKmax + 6), s,
+                        /*may_allocate=*/false);
   if (e != hipSuccess) return hip_fail(e, "backward launch");
   return GFC_OK;
 }
