@@ -11,15 +11,28 @@ method, one fused kernel launch) with inputs resident in device memory.  The
 PSF-FT cache is filled before timing (a cold, once-per-PSF step) and timed
 separately.  Printed: ONE JSON line (see the keys below).
 
-    python bench.py [--gpus 1] [--steps 20] [--warmup 3]
+Order of a run:
+  1. CPU leg (before the GPU is touched): the FP64 oracle, one single-threaded
+     process per core of this process's CPU share, timed on a seeded sample
+     of the workload (cpu_baseline); the same processes then compute, untimed,
+     the reference samples that gate every other reported number.
+  2. Rate probes of the device (FMA, v_exp_f32, HBM write and copy): the
+     measured roofline denominators.  They also bring the clocks up.
+  3. W warm-up steps, then K timed steps (HIP events on the launch stream).
+  4. Parity of the timed output, the plain per-request launches, serving,
+     and the other workloads, each with a parity record from its own launch.
+
+    python bench.py [--gpus 1] [--steps 100] [--warmup 30]
 """
 
 from __future__ import annotations
 
 import argparse
+import io
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -35,7 +48,10 @@ METRIC = "stamps/sec (64², K=8 MoG) batched vs plain at ≤1e-5 peak err; p99 l
 # MI355X peaks used for the roofline (published / derived from unit counts).
 CU, SIMD_PER_CU, LANES_PER_SIMD, CLOCK_HZ = 256, 4, 16, 2.4e9
 FP32_FMA_NONPACKED_TFLOPS = CU * SIMD_PER_CU * LANES_PER_SIMD * 2 * CLOCK_HZ / 1e12   # 78.6
+FP32_PUBLISHED_TFLOPS = 157.3   # counts packed FP32 FMAs, which this build does not use
 HBM_GBPS = 8000.0
+TOL_PEAK = 1e-5                 # forward parity bar: max |gpu - oracle| <= TOL_PEAK x peak
+CPU_SHARE = 16                  # CPUs a one-GPU machine gives this process
 
 KQ = -2.0 * math.pi**2 * math.log2(math.e)
 
@@ -68,6 +84,20 @@ def algorithmic_flops_per_stamp(W, kf, kr):
     return n_eval * (4.0 + 4.0 * kf) + 14.0 * H + 2.5 * W * W * math.log2(W * W) + 7.0 * W * W * kr
 
 
+def algorithmic_issue_slots(W, kf, kr):
+    """(VALU issue slots, exponentials) per stamp of the same algorithm when
+    every FMA-able pair is one instruction: quadratic form 2 per evaluation
+    point, per Fourier component a multiply, an exponential and an FMA; 10
+    per bin for phase x PSF x flux; (5/3) W^2 log2 W^2 for the inverse FFT
+    with FMA butterflies (2.5 W^2 log2 W^2 FLOP at 1.5 FLOP per slot);
+    per real-space component and pixel two FMAs, an exponential and an FMA."""
+    H = W * (W // 2 + 1)
+    n_eval = H + (W // 2 + 1) + W + 2
+    slots = n_eval * (2.0 + 3.0 * kf) + 10.0 * H + (5.0 / 3.0) * W * W * math.log2(W * W) + 4.0 * W * W * kr
+    exps = n_eval * kf + W * W * kr
+    return slots, exps
+
+
 # ---------------------------------------------------------------- HBM traffic record
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_render_small_kernel_64.txt")
 
@@ -96,60 +126,264 @@ def measured_traffic():
     return float(rec["fetch_bytes_per_launch"]) + float(rec["write_bytes_per_launch"])
 
 
-# ---------------------------------------------------------------- CPU baseline (oracle)
-def _oracle_worker(args):
-    idx, seed_n = args
+# ---------------------------------------------------------------- CPU leg: the oracle
+# Reference samples gating the other reported numbers: (job, workload size, sample size).
+REF_JOBS = {
+    "mixed": 120, "large": 24, "lanczos": 48, "sersic": 48, "composite": 48, "eigen": 36, "backward": 24,
+}
+BWD_NOISE_SEED = wl.SEED_BASE + 55    # upstream gradient of the adjoint line: unit-normal noise
+
+
+def ref_indices(job, n_total, k):
+    """Seeded sample of a workload; for the mixed and large workloads it is
+    stratified by stamp size (equal numbers per size)."""
+    rng = np.random.Generator(np.random.PCG64(7000 + sorted(REF_JOBS).index(job)))
+    if job in ("mixed", "large"):
+        cfg = wl.config2() if job == "mixed" else wl.config3()
+        Ws = sorted(set(int(w) for w in cfg["gal"].W))
+        per = k // len(Ws)
+        idx = []
+        for W in Ws:
+            idx += rng.choice(np.nonzero(cfg["gal"].W == W)[0], per, replace=False).tolist()
+        return np.array(sorted(idx))
+    return np.sort(rng.choice(n_total, k, replace=False))
+
+
+def _oracle_job(job, idx, n_metric):
+    """The oracle's stamps (or gradients) for one reference job."""
+    import oracle as o
+    from oracle import eigen as oe
+    from oracle import lanczos as ol
+    from oracle import sersic as osr
+
+    if job == "metric":
+        cfg = wl.config_metric(n_metric)
+        return o.render_batch(cfg["psf"].astype(np.float64), cfg["mix"].as_f32(), cfg["gal"], idx=idx)
+    if job in ("mixed", "large"):
+        cfg = wl.config2() if job == "mixed" else wl.config3()
+        return o.render_batch(cfg["psf"].astype(np.float64), cfg["mix"].as_f32(), cfg["gal"],
+                              psf_gauss=cfg.get("psf_gauss"), idx=idx)
+    if job == "lanczos":
+        cfg = wl.config_metric()
+        P = cfg["psf"].astype(np.float64)
+        ph, g = o.psf_spectrum(P, 64), o.psf_gauss_moments(P)
+        amp, var = cfg["mix"].as_f32().table(0)
+        out = []
+        for i in idx:
+            p = cfg["gal"].params(int(i))
+            out.append(ol.render_stamp_lanczos(ph, g, amp, var, p["x"], p["y"], p["flux"], p["r_e"], p["e1"],
+                                               p["e2"], 64, 8))
+        return out
+    if job == "sersic":
+        cfg = wl.config_sersic()
+        fam = {k: np.asarray(v, np.float32).astype(np.float64) for k, v in cfg["family"].items()}
+        return osr.render_batch_sersic(cfg["psf"].astype(np.float64), fam, cfg["gal"], cfg["sersic_n"], idx=idx)
+    if job == "composite":
+        cfg = wl.config_composite()
+        P = cfg["psf"].astype(np.float64)
+        ph, g = o.psf_spectrum(P, 64), o.psf_gauss_moments(P)
+        m = cfg["mix"].as_f32()
+        (ad, vd), (ab, vb) = m.table(0), m.table(1)
+        out = []
+        for i in idx:
+            p = cfg["gal"].params(int(i))
+            a, v = osr.composite_mixture(ad, vd, ab, vb, float(cfg["bulge_frac"][i]), float(cfg["bulge_rho"][i]))
+            out.append(o.render_stamp(ph, g, a, v, p["x"], p["y"], p["flux"], p["r_e"], p["e1"], p["e2"], 64))
+        return out
+    if job == "eigen":
+        cfg = wl.config_eigen()
+        eig = dict(cfg["eig"], comps=np.asarray(cfg["eig"]["comps"], np.float32).astype(np.float64))
+        return oe.render_batch_eigen(eig, cfg["mix"].as_f32(), cfg["gal"], cfg["psf_x"], cfg["psf_y"], idx=idx)
+    if job == "backward":
+        cfg = wl.config5()
+        P = cfg["psf"].astype(np.float64)
+        ph, g = o.psf_spectrum(P, 64), o.psf_gauss_moments(P)
+        amp, var = cfg["mix"].as_f32().table(0)
+        noise = wl.generate.noise_field(BWD_NOISE_SEED, len(cfg["gal"]), 64)
+        out = []
+        for i in idx:
+            p = cfg["gal"].params(int(i))
+            _, J = o.render_stamp_jacobian(ph, g, amp, var, p["x"], p["y"], p["flux"], p["r_e"], p["e1"],
+                                           p["e2"], 64)
+            lg = o.loss_gradient(noise[i].astype(np.float64), J)
+            out.append(np.array([lg[k] for k in ("x", "y", "flux", "log_re", "e1", "e2")]))
+        return out
+    raise ValueError(job)
+
+
+def oracle_worker_main():
+    """`bench.py --oracle-worker`: reads a job list (JSON) on stdin, runs the
+    oracle single-threaded and writes an .npz to stdout."""
+    spec = json.loads(sys.stdin.read())
     import threadpoolctl
 
-    import oracle as o
-
+    res = {}
     with threadpoolctl.threadpool_limits(1):
-        cfg = wl.config_metric(seed_n)
-        P = cfg["psf"].astype(np.float64)
-        t0 = time.perf_counter()
-        imgs = o.render_batch(P, cfg["mix"].as_f32(), cfg["gal"], idx=idx)
-        dt = time.perf_counter() - t0
-    return idx, np.stack(imgs), dt
+        for job, idx, timed in spec["jobs"]:
+            t0 = time.perf_counter()
+            out = _oracle_job(job, [int(i) for i in idx], spec["n_metric"])
+            dt = time.perf_counter() - t0
+            for i, a in zip(idx, out):
+                res[f"{job}/{i}"] = np.asarray(a, np.float64)
+            if timed:
+                res[f"__cpu_s__/{job}/{idx[0]}"] = np.array(dt)
+    buf = io.BytesIO()
+    np.savez(buf, **res)
+    sys.stdout.buffer.write(buf.getvalue())
+    sys.stdout.buffer.flush()
 
 
-def cpu_baseline(n_total, sample, workers):
-    """Times the FP64 oracle (unchanged) on a seeded sample of the workload,
-    one single-threaded process per core.  Runs before the GPU is touched."""
-    import multiprocessing as mp
-
-    rng = np.random.Generator(np.random.PCG64(2024))
-    idx = np.sort(rng.choice(n_total, size=sample, replace=False))
-    chunks = [(list(map(int, c)), n_total) for c in np.array_split(idx, workers)]
-    ctx = mp.get_context("fork")
+def _run_workers(job_lists, n_metric):
+    """One child process per job list; returns (merged results, wall s).
+    Every child is waited for, so none outlives the call."""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
     t0 = time.perf_counter()
-    with ctx.Pool(workers) as pool:
-        res = pool.map(_oracle_worker, chunks)
+    procs = []
+    for jobs in job_lists:
+        p = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--oracle-worker"], stdin=subprocess.PIPE,
+                             stdout=subprocess.PIPE, env=env)
+        procs.append(p)
+    outs = []
+    try:
+        for p, jobs in zip(procs, job_lists):
+            p.stdin.write(json.dumps(dict(jobs=jobs, n_metric=n_metric)).encode())
+            p.stdin.close()
+        for p in procs:
+            data = p.stdout.read()
+            rc = p.wait()
+            if rc != 0:
+                raise RuntimeError(f"oracle worker exited with {rc}")
+            outs.append(data)
+    finally:
+        for p in procs:
+            if p.poll() is None:
+                p.kill()
+                p.wait()
     wall = time.perf_counter() - t0
-    stamps = {}
-    cpu_s = 0.0
-    for ii, imgs, dt in res:
-        cpu_s += dt
-        for j, i in enumerate(ii):
-            stamps[i] = imgs[j]
-    return dict(value=sample / wall, unit="stamps/s", cores=workers, kind="oracle",
-                sample=f"{sample} seeded stamps of the 100k workload, FP64 oracle, {workers} "
-                       f"single-threaded processes, {cpu_s:.1f} CPU-s in {wall:.2f} s wall"), stamps
+    merged = {}
+    for data in outs:
+        with np.load(io.BytesIO(data)) as z:
+            for k in z.files:
+                merged[k] = z[k]
+    return merged, wall
+
+
+def cpu_leg(n_metric, sample, workers, other):
+    """The oracle, unchanged, timed on a seeded sample of the metric workload
+    in `workers` single-threaded processes (cpu_baseline); then the untimed
+    reference samples of the other numbers.  Runs before the GPU is touched."""
+    rng = np.random.Generator(np.random.PCG64(2024))
+    idx = np.sort(rng.choice(n_metric, size=sample, replace=False))
+    lists = [[["metric", c.tolist(), True]] for c in np.array_split(idx, workers)]
+    res, wall = _run_workers(lists, n_metric)
+    times = [float(v) for k, v in res.items() if k.startswith("__cpu_s__")]
+    cpu_s, span = sum(times), max(times)
+    metric_refs = {int(k.split("/")[1]): v for k, v in res.items() if k.startswith("metric/")}
+    host_cpus = os.cpu_count() or 1
+    share = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else host_cpus
+    cpu = dict(value=round(sample / span, 1), unit="stamps/s", cores=workers, kind="oracle",
+               host_cpu_count=host_cpus, cpus_available=share,
+               sample=f"{sample} seeded stamps of the 100k workload, FP64 oracle, {workers} single-threaded "
+                      f"processes (host os.cpu_count() {host_cpus}, {share} CPUs in this process's affinity, "
+                      f"of which a one-GPU box grants {CPU_SHARE}); {cpu_s:.1f} CPU-s, the slowest process "
+                      f"{span:.2f} s in the oracle (value = sample / that), {wall:.2f} s wall with start-up")
+    refs = {}
+    if other:
+        jobs = []
+        for job, k in REF_JOBS.items():
+            n_total = {"lanczos": 100_000, "sersic": 100_000, "composite": 100_000, "eigen": 100_000,
+                       "backward": 10_000}.get(job, 0)
+            ii = ref_indices(job, n_total, k)
+            refs[job] = ii
+            for c in np.array_split(ii, max(1, min(workers, len(ii) // 4))):
+                if len(c):
+                    jobs.append([job, c.tolist(), False])
+        lists = [jobs[i::workers] for i in range(workers) if jobs[i::workers]]
+        res2, wall2 = _run_workers(lists, n_metric)
+        refs = {job: (ii, [res2[f"{job}/{i}"] for i in ii]) for job, ii in refs.items()}
+        log(f"cpu leg: reference samples for {len(refs)} workloads in {wall2:.1f} s")
+    return cpu, metric_refs, refs
+
+
+def stamp_parity(gpu_rows, ref_rows):
+    errs = [float(np.abs(g - r).max() / np.abs(r).max()) for g, r in zip(gpu_rows, ref_rows)]
+    return dict(n_checked=len(errs), max_err_over_peak=max(errs), tol=TOL_PEAK,
+                passed=bool(max(errs) <= TOL_PEAK))
+
+
+# ---------------------------------------------------------------- device rate probes
+def rate_probes(dev):
+    """Measured denominators: FP32 FMA issue rate, v_exp_f32 alone and
+    interleaved with FMAs, streamed HBM write and copy."""
+    import ctypes
+
+    import torch
+
+    path = os.path.join(ROOT, "paper_2012_15797_amd", "libgfc_microbench.so")
+    mb = ctypes.CDLL(path)
+    D = ctypes.POINTER(ctypes.c_double)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    sink = torch.zeros(4, device=dev)
+    sp = ctypes.c_void_p(sink.data_ptr())
+    out = {}
+
+    def chk(rc, what):
+        if rc != 0:
+            raise RuntimeError(f"{what} probe failed: {rc}")
+
+    v = ctypes.c_double()
+    mb.gfc_mb_fma.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, D]
+    chk(mb.gfc_mb_fma(5, sp, stream, ctypes.byref(v)), "fma")
+    fma = v.value
+    out["fp32_fma_tflops"] = round(2 * fma / 1e12, 2)
+    mb.gfc_mb_exp.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, D]
+    chk(mb.gfc_mb_exp(5, sp, stream, ctypes.byref(v)), "exp")
+    out["exp_only_g_per_s"] = round(v.value / 1e9, 1)
+    out["exp_only_fma_slots"] = round(fma / v.value, 3)
+    mb.gfc_mb_exp_fma.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, D, D]
+    mixed = {}
+    for F in (1, 2, 3, 4):
+        e, f = ctypes.c_double(), ctypes.c_double()
+        chk(mb.gfc_mb_exp_fma(F, 5, sp, stream, ctypes.byref(e), ctypes.byref(f)), "exp+fma")
+        # issue slots one exponential costs beside F FMAs, in units of one FMA's slot
+        mixed[F] = round(fma / e.value - F, 3)
+    out["exp_fma_slots_with_F_fmas"] = mixed
+    nbytes = 2 << 30
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    mb.gfc_mb_hbm_write.argtypes = [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p, D]
+    chk(mb.gfc_mb_hbm_write(ctypes.c_void_p(b.data_ptr()), nbytes, 5, stream, ctypes.byref(v)), "write")
+    out["hbm_write_gbps"] = round(v.value / 1e9, 1)
+    mb.gfc_mb_hbm_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
+                                   ctypes.c_void_p, D]
+    chk(mb.gfc_mb_hbm_copy(ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(a.data_ptr()), nbytes, 5, stream,
+                           ctypes.byref(v)), "copy")
+    out["hbm_copy_gbps"] = round(v.value / 1e9, 1)
+    del a, b
+    torch.cuda.synchronize()
+    return out
 
 
 # ---------------------------------------------------------------- main
 def main():
+    if "--oracle-worker" in sys.argv:
+        oracle_worker_main()
+        return
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--n", type=int, default=100_000)
-    ap.add_argument("--cpu-sample", type=int, default=24000)
+    ap.add_argument("--cpu-sample", type=int, default=20000)
     ap.add_argument("--cpu-workers", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=3.0,
-                    help="length of the Poisson request trace replayed against the server (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="length of the mixed-size, 64-PSF Poisson request trace replayed against the "
+                         "server, batched and plain (0: skip serving)")
     ap.add_argument("--no-other", action="store_true", help="skip the other-workload throughput table")
+    ap.add_argument("--no-probes", action="store_true", help="skip the device rate probes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (for scaling HBM counters)")
     args = ap.parse_args()
@@ -168,11 +402,12 @@ def main():
     kf, kr = routing_counts(gal, var, W)
     flops_stamp = algorithmic_flops_per_stamp(W, kf, kr)
 
-    cpu, oracle_stamps = None, {}
+    cpu, oracle_stamps, refs = None, {}, {}
     if not args.no_cpu_baseline:
-        workers = args.cpu_workers or min(16, os.cpu_count() or 1)
-        log(f"cpu baseline: oracle on {args.cpu_sample} stamps with {workers} processes")
-        cpu, oracle_stamps = cpu_baseline(args.n, args.cpu_sample, workers)
+        share = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+        workers = args.cpu_workers or max(1, min(CPU_SHARE, share))
+        log(f"cpu leg: oracle on {args.cpu_sample} stamps with {workers} processes")
+        cpu, oracle_stamps, refs = cpu_leg(args.n, args.cpu_sample, workers, not args.no_other)
         log(f"cpu baseline: {cpu['value']:.1f} stamps/s")
 
     import torch
@@ -180,6 +415,9 @@ def main():
     import paper_2012_15797_amd as gfc
 
     dev = torch.device("cuda", 0)
+    probes = None if args.no_probes else rate_probes(dev)
+    if probes:
+        log(f"rate probes: {probes}")
     ctx = gfc.Context.default(0)
     psf = gfc.Psf(ctx, cfg["psf"])
     mix = gfc.Mixture.from_workload(ctx, mixf)
@@ -200,7 +438,7 @@ def main():
     torch.cuda.synchronize()
     log(f"warmup done ({args.warmup} steps)")
 
-    stream = torch.cuda.current_stream(dev)
+    stream = torch.cuda.current_stream(dev)     # the stream the library launches on
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -211,35 +449,57 @@ def main():
         ev[i][1].record(stream)
     torch.cuda.synchronize()
     wall_s = time.perf_counter() - t_start
-    kern_ms = [a.elapsed_time(b) for a, b in ev]
+    kern_ms = np.array([a.elapsed_time(b) for a, b in ev])
     ms_per_step = wall_s * 1e3 / args.steps
     value = args.n / (ms_per_step / 1e3)
-    avg_kern_ms = float(np.mean(kern_ms))
-    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, kernel {avg_kern_ms:.3f} ms avg "
-        f"(min {min(kern_ms):.3f})")
+    avg_kern_ms = float(kern_ms.mean())
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, kernel mean {avg_kern_ms:.3f} ms, "
+        f"median {np.median(kern_ms):.3f}, min {kern_ms.min():.3f}")
 
-    achieved_tflops = float(flops_stamp.sum()) / (avg_kern_ms * 1e-3) / 1e12
+    flops_launch = float(flops_stamp.sum())
+    achieved_tflops = flops_launch / (avg_kern_ms * 1e-3) / 1e12
     roofline = dict(bound="alu", achieved=round(achieved_tflops, 3), peak=round(FP32_FMA_NONPACKED_TFLOPS, 2),
-                    unit="TFLOP/s", frac=round(achieved_tflops / FP32_FMA_NONPACKED_TFLOPS, 4), traffic=measured_traffic(),
+                    unit="TFLOP/s", frac=round(achieved_tflops / FP32_FMA_NONPACKED_TFLOPS, 4),
+                    traffic=measured_traffic(),
                     kernel="render_small_kernel<64, false, false>",
                     flops_per_stamp=round(float(flops_stamp.mean()), 1),
+                    peak_note="FP32 vector FMA peak without packed instructions: 256 CU x 4 SIMD x 16 lanes x "
+                              "2 FLOP x 2.4 GHz",
+                    published_peak=FP32_PUBLISHED_TFLOPS,
+                    frac_published=round(achieved_tflops / FP32_PUBLISHED_TFLOPS, 4),
+                    achieved_median_time=round(flops_launch / (float(np.median(kern_ms)) * 1e-3) / 1e12, 3),
                     algorithmic_bytes=args.n * (4 * W * W + 28),
-                    hbm_gbps=round(args.n * (4 * W * W + 28) / (avg_kern_ms * 1e-3) / 1e9, 1))
+                    hbm_gbps=round(args.n * (4 * W * W + 28) / (avg_kern_ms * 1e-3) / 1e9, 1),
+                    hbm_frac=round(args.n * (4 * W * W + 28) / (avg_kern_ms * 1e-3) / 1e9 / HBM_GBPS, 4))
+    if probes:
+        meas = probes["fp32_fma_tflops"]
+        roofline.update(measured_peak=meas, frac_measured=round(achieved_tflops / meas, 4),
+                        hbm_measured_write_gbps=probes["hbm_write_gbps"])
+        # issue-slot model with the measured cost of an exponential beside two FMAs (the mixture loop's mix)
+        slots, exps = algorithmic_issue_slots(W, kf, kr)
+        c_exp = probes["exp_fma_slots_with_F_fmas"][2]
+        t_model = float((slots + (c_exp - 1.0) * exps).sum()) / (meas * 1e12 / 2.0)
+        roofline["issue_model"] = dict(
+            slots_per_stamp=round(float(slots.mean()), 1), exps_per_stamp=round(float(exps.mean()), 1),
+            exp_cost_slots=c_exp, time_ms=round(t_model * 1e3, 4),
+            frac=round(t_model / (avg_kern_ms * 1e-3), 4),
+            note="time the algorithm's minimal VALU issue needs at the measured FMA rate, an exponential "
+                 "costing the measured slots beside FMAs; frac = that time / kernel time")
 
     parity = None
     if oracle_stamps:
         idx = sorted(oracle_stamps)
         sel = out[torch.as_tensor(idx, device=dev)].cpu().numpy().astype(np.float64)
-        errs = [np.abs(sel[j] - oracle_stamps[i]).max() / np.abs(oracle_stamps[i]).max()
-                for j, i in enumerate(idx)]
-        parity = dict(n_checked=len(idx), max_err_over_peak=float(max(errs)), tol=1e-5,
-                      passed=bool(max(errs) <= 1e-5))
-        log(f"parity on {len(idx)} stamps: max err/peak {max(errs):.2e}")
+        parity = stamp_parity(sel, [oracle_stamps[i] for i in idx])
+        log(f"parity on {len(idx)} stamps: max err/peak {parity['max_err_over_peak']:.2e}")
 
     plain = None
     if not args.no_plain:
-        plain = plain_per_request(gfc, ctx, psf, mix, gal, W, dev)
+        plain = plain_per_request(gfc, ctx, psf, mix, gal, W, dev, oracle_stamps)
         log(f"plain per-request launches: {plain['value']:.3e} stamps/s over {plain['requests']} requests")
+    del out
+    psf.close()
+    mix.close()
 
     serving = None
     if args.serve_seconds > 0:
@@ -247,8 +507,8 @@ def main():
 
     other = None
     if not args.no_other:
-        other = size_throughput(gfc, ctx, dev)
-        log(f"other workloads: {other}")
+        other = size_throughput(gfc, ctx, dev, refs)
+        log(f"other workloads: {json.dumps(other)}")
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
@@ -268,26 +528,42 @@ def main():
                     psf="64x64 Moffat beta=3 FWHM 4.5 px + 1% Gaussian halo sigma 8 px",
                     routing="hybrid (smoothstep ramp n in [3,4])",
                     mean_K_F=round(float(kf.mean()), 3), mean_K_R=round(float(kr.mean()), 3)),
-        roofline=roofline, cpu_baseline=cpu, parity=parity,
+        roofline=roofline, cpu_baseline=cpu, parity=parity, rate_probes=probes,
         plain=plain, serving=serving, other_workloads=other, psf_cache_fill_ms=round(psf_cache_ms, 3),
-        kernel_ms=dict(mean=round(avg_kern_ms, 4), min=round(min(kern_ms), 4), max=round(max(kern_ms), 4)),
+        kernel_ms=dict(mean=round(avg_kern_ms, 4), median=round(float(np.median(kern_ms)), 4),
+                       min=round(float(kern_ms.min()), 4), max=round(float(kern_ms.max()), 4)),
     )
     print(json.dumps(rec), flush=True)
 
 
+def parity_of_rows(out, refs, dev):
+    """Parity of the rows of `out` for which the CPU leg holds oracle stamps."""
+    import torch
+
+    if not refs:
+        return None
+    idx = sorted(refs)
+    rows = out[torch.as_tensor(idx, device=dev)].cpu().numpy().astype(np.float64)
+    return stamp_parity(rows, [refs[i] for i in idx])
+
+
 def serving_benchmark(gfc, ctx, seconds):
-    """Open-loop replay of the 64x64 serving trace (Poisson arrivals at
-    2,000 requests/s, 1..4096 galaxies per request, DEV8, the throughput
-    workload's PSF) against the continuous-batching server and against the
-    plain mode (one launch per request, FIFO on one stream), with the same
-    32 GB device-memory budget."""
+    """Open-loop replays of Poisson request traces against the
+    continuous-batching server and against the plain mode (one launch per
+    request, FIFO on one stream), with the same 32 GB device-memory budget:
+    the full serving configuration (2,000 requests/s for `seconds`, 64
+    resident PSFs, stamps 16..256), and the 64x64 one-PSF variant at the
+    nominal and a saturating rate."""
     from paper_2012_15797_amd.serving import Server, replay_trace
 
     out = {}
-    for label, rate, secs, restricted in (("", 2000.0, seconds, True),
-                                          ("saturated_", 20000.0, min(seconds, 1.0), True),
-                                          ("mixed_sizes_", 2000.0, min(seconds, 1.0), False)):
+    for label, rate, secs, restricted in (("", 2000.0, seconds, False),
+                                          ("restricted64_", 2000.0, min(seconds, 3.0), True),
+                                          ("saturated64_", 20000.0, min(seconds, 1.0), True)):
+        t0 = time.perf_counter()
         tr = wl.config4_trace(duration_s=secs, rate_hz=rate, restricted=restricted)
+        log(f"serving trace {label or 'full_'}: {len(tr['requests'])} requests drawn in "
+            f"{time.perf_counter() - t0:.1f} s")
         psfs = [gfc.Psf(ctx, p) for p in tr["psfs"]]
         mix = gfc.Mixture.from_workload(ctx, tr["mix"].as_f32())
         for p in psfs:
@@ -301,92 +577,104 @@ def serving_benchmark(gfc, ctx, seconds):
             srv = Server(ctx, mem_budget_bytes=32 << 30, n_streams=streams, max_batch_stamps=max_batch)
             out[label + name] = replay_trace(srv, tr["requests"], psfs, mix)
             srv.close()
-            log(f"serving {label or 'nominal_'}{name}: {out[label + name]}")
+            log(f"serving {label or 'full_'}{name}: {out[label + name]}")
         for p in psfs:
             p.close()
         mix.close()
     return out
 
 
-def size_throughput(gfc, ctx, dev, reps=5):
+def size_throughput(gfc, ctx, dev, refs, reps=5):
     """Forward stamps/s per stamp size on the mixed-size and large-galaxy
-    workloads (one launch per size bin), and the adjoint on the
-    differentiation workload."""
+    workloads (one launch per size bin), the 64x64 workload with Lanczos
+    shifting, general Sersic, composites and the eigen-PSF, and the adjoint
+    on the differentiation workload.  Every line carries the parity of a
+    seeded sample of its own last launch against the CPU leg's oracle."""
     import torch
 
-    res = {}
-    for cname, cfg in (("mixed-32-64-128", wl.config2()), ("large-128-256", wl.config3())):
-        psf = gfc.Psf(ctx, cfg["psf"], cfg.get("psf_gauss"))
-        mix = gfc.Mixture.from_workload(ctx, cfg["mix"].as_f32())
-        g = cfg["gal"]
-        tot_ms, tot_n = 0.0, 0
-        for W in sorted(set(int(w) for w in g.W)):
-            sub = g.subset(np.nonzero(g.W == W)[0])
-            d = lambda a: torch.as_tensor(a).to(dev)
-            args = [d(a) for a in (sub.x, sub.y, sub.flux, sub.r_e, sub.e1, sub.e2)]
-            mid = d(sub.mix_id)
-            out = torch.empty((len(sub), W, W), dtype=torch.float32, device=dev)
-            psf.prepare(W)
-            gfc.gfc_render_stamps(ctx, psf, mix, *args, W, mix_id=mid, out=out)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(reps):
-                gfc.gfc_render_stamps(ctx, psf, mix, *args, W, mix_id=mid, out=out)
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / reps
-            res[f"{cname}/W{W}"] = dict(stamps=len(sub), ms=round(ms, 4), stamps_per_s=round(len(sub) / ms * 1e3, 1))
-            tot_ms += ms
-            tot_n += len(sub)
-            del out
-        res[cname] = dict(stamps=tot_n, ms=round(tot_ms, 4), stamps_per_s=round(tot_n / tot_ms * 1e3, 1))
-        psf.close()
-        mix.close()
-    # Lanczos-3 sub-pixel shift instead of the Fourier phase: the throughput workload
-    cfg = wl.config_metric()
-    g = cfg["gal"]
-    psf = gfc.Psf(ctx, cfg["psf"])
-    mix = gfc.Mixture.from_workload(ctx, cfg["mix"].as_f32())
     d = lambda a: torch.as_tensor(a).to(dev)
-    args = [d(a) for a in (g.x, g.y, g.flux, g.r_e, g.e1, g.e2)]
-    out = torch.empty((len(g), 64, 64), dtype=torch.float32, device=dev)
-    for _ in range(3):
-        gfc.gfc_render_stamps(ctx, psf, mix, *args, 64, out=out, flags=gfc.GFC_SHIFT_LANCZOS3)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps * 4):
-        gfc.gfc_render_stamps(ctx, psf, mix, *args, 64, out=out, flags=gfc.GFC_SHIFT_LANCZOS3)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / (reps * 4)
-    res["lanczos3-dev8-64x64-100k"] = dict(stamps=len(g), ms=round(ms, 4), stamps_per_s=round(len(g) / ms * 1e3, 1))
-    del out
-    psf.close()
-    mix.close()
-    # general Sersic (mixture interpolated per galaxy) and bulge + disk composites, 100k at 64x64
-    def timed(fn):
+
+    def timed(fn, n_reps):
         for _ in range(3):
             fn()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        for _ in range(reps * 4):
+        for _ in range(n_reps):
             fn()
         e1.record()
         torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / (reps * 4)
+        return e0.elapsed_time(e1) / n_reps
 
+    def line(n, ms, **kw):
+        return dict(stamps=n, ms=round(ms, 4), stamps_per_s=round(n / ms * 1e3, 1), **kw)
+
+    def rows_parity(job, out_rows_of):
+        """Parity of the job's reference sample; out_rows_of(global indices) -> rows."""
+        if job not in refs:
+            return None
+        ii, ref = refs[job]
+        return stamp_parity(out_rows_of(ii), ref)
+
+    res = {}
+    for cname, job, cfg in (("mixed-32-64-128", "mixed", wl.config2()), ("large-128-256", "large", wl.config3())):
+        psf = gfc.Psf(ctx, cfg["psf"], cfg.get("psf_gauss"))
+        mix = gfc.Mixture.from_workload(ctx, cfg["mix"].as_f32())
+        g = cfg["gal"]
+        tot_ms, tot_n = 0.0, 0
+        worst = []
+        for W in sorted(set(int(w) for w in g.W)):
+            sel = np.nonzero(g.W == W)[0]
+            sub = g.subset(sel)
+            args = [d(a) for a in (sub.x, sub.y, sub.flux, sub.r_e, sub.e1, sub.e2)]
+            mid = d(sub.mix_id)
+            out = torch.empty((len(sub), W, W), dtype=torch.float32, device=dev)
+            psf.prepare(W)
+            ms = timed(lambda: gfc.gfc_render_stamps(ctx, psf, mix, *args, W, mix_id=mid, out=out), reps)
+            par = None
+            if job in refs:
+                ii, ref = refs[job]
+                keep = [(j, int(i)) for j, i in enumerate(ii) if g.W[i] == W]
+                pos = np.searchsorted(sel, [i for _, i in keep])
+                rows = out[torch.as_tensor(pos, device=dev)].cpu().numpy().astype(np.float64)
+                par = stamp_parity(rows, [ref[j] for j, _ in keep])
+                worst.append(par)
+            res[f"{cname}/W{W}"] = line(len(sub), ms, parity=par)
+            tot_ms += ms
+            tot_n += len(sub)
+            del out
+        par = None
+        if worst:
+            par = dict(n_checked=sum(p["n_checked"] for p in worst),
+                       max_err_over_peak=max(p["max_err_over_peak"] for p in worst), tol=TOL_PEAK,
+                       passed=all(p["passed"] for p in worst))
+        res[cname] = line(tot_n, tot_ms, parity=par)
+        psf.close()
+        mix.close()
+
+    # Lanczos-3 sub-pixel shift instead of the Fourier phase: the throughput workload
+    cfg = wl.config_metric()
+    g = cfg["gal"]
+    psf = gfc.Psf(ctx, cfg["psf"])
+    mix = gfc.Mixture.from_workload(ctx, cfg["mix"].as_f32())
+    args = [d(a) for a in (g.x, g.y, g.flux, g.r_e, g.e1, g.e2)]
+    out = torch.empty((len(g), 64, 64), dtype=torch.float32, device=dev)
+    rows = lambda ii: out[torch.as_tensor(ii, device=dev)].cpu().numpy().astype(np.float64)
+    ms = timed(lambda: gfc.gfc_render_stamps(ctx, psf, mix, *args, 64, out=out, flags=gfc.GFC_SHIFT_LANCZOS3),
+               reps * 4)
+    res["lanczos3-dev8-64x64-100k"] = line(len(g), ms, parity=rows_parity("lanczos", rows))
+    psf.close()
+    mix.close()
+
+    # general Sersic (mixture interpolated per galaxy) and bulge + disk composites, 100k at 64x64
     cfg = wl.config_sersic()
     g = cfg["gal"]
     psf = gfc.Psf(ctx, cfg["psf"])
     fam = gfc.SersicFamily.from_workload(ctx, cfg["family"])
     args = [d(a) for a in (g.x, g.y, g.flux, g.r_e, g.e1, g.e2)]
     sn = d(cfg["sersic_n"])
-    out = torch.empty((len(g), 64, 64), dtype=torch.float32, device=dev)
-    ms = timed(lambda: gfc.gfc_render_stamps_sersic(ctx, psf, fam, *args, sn, 64, out=out))
-    res["sersic8-64x64-100k"] = dict(stamps=len(g), ms=round(ms, 4), stamps_per_s=round(len(g) / ms * 1e3, 1))
+    ms = timed(lambda: gfc.gfc_render_stamps_sersic(ctx, psf, fam, *args, sn, 64, out=out), reps * 4)
+    res["sersic8-64x64-100k"] = line(len(g), ms, parity=rows_parity("sersic", rows))
     psf.close()
     fam.close()
     cfg = wl.config_composite()
@@ -395,64 +683,59 @@ def size_throughput(gfc, ctx, dev, reps=5):
     mix = gfc.Mixture.from_workload(ctx, cfg["mix"].as_f32())
     args = [d(a) for a in (g.x, g.y, g.flux, g.r_e, g.e1, g.e2)]
     fr, rh = d(cfg["bulge_frac"]), d(cfg["bulge_rho"])
-    ms = timed(lambda: gfc.gfc_render_stamps_composite(ctx, psf, mix, 0, 1, *args, fr, rh, 64, out=out))
-    res["composite14-64x64-100k"] = dict(stamps=len(g), ms=round(ms, 4), stamps_per_s=round(len(g) / ms * 1e3, 1))
-    del out
+    ms = timed(lambda: gfc.gfc_render_stamps_composite(ctx, psf, mix, 0, 1, *args, fr, rh, 64, out=out), reps * 4)
+    res["composite14-64x64-100k"] = line(len(g), ms, parity=rows_parity("composite", rows))
     psf.close()
     mix.close()
+
     # spatially varying PSF: 6 eigen components (degree-2 polynomial), 100k stamps at 64x64
     cfg = wl.config_eigen()
     g, e = cfg["gal"], cfg["eig"]
     psf = gfc.Psf.eigen(ctx, e["comps"], e["coef"], e["degree"], e["norm"])
     mix = gfc.Mixture.from_workload(ctx, cfg["mix"].as_f32())
-    d = lambda a: torch.as_tensor(a).to(dev)
     args = [d(a) for a in (g.x, g.y, g.flux, g.r_e, g.e1, g.e2)]
     px, py = d(cfg["psf_x"]), d(cfg["psf_y"])
-    out = torch.empty((len(g), 64, 64), dtype=torch.float32, device=dev)
-    for _ in range(3):
-        gfc.gfc_render_stamps(ctx, psf, mix, *args, 64, out=out, psf_x=px, psf_y=py)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps * 4):
-        gfc.gfc_render_stamps(ctx, psf, mix, *args, 64, out=out, psf_x=px, psf_y=py)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / (reps * 4)
-    res["eigenpsf6-dev8-64x64-100k"] = dict(stamps=len(g), ms=round(ms, 4), stamps_per_s=round(len(g) / ms * 1e3, 1))
+    ms = timed(lambda: gfc.gfc_render_stamps(ctx, psf, mix, *args, 64, out=out, psf_x=px, psf_y=py), reps * 4)
+    res["eigenpsf6-dev8-64x64-100k"] = line(len(g), ms, parity=rows_parity("eigen", rows))
     del out
     psf.close()
     mix.close()
-    # adjoint on the differentiation workload (upstream gradient: unit normal noise)
+
+    # adjoint on the differentiation workload (upstream gradient: seeded unit-normal noise)
     cfg = wl.config5()
     g = cfg["gal"]
     psf = gfc.Psf(ctx, cfg["psf"])
     mix = gfc.Mixture.from_workload(ctx, cfg["mix"].as_f32())
-    d = lambda a: torch.as_tensor(a).to(dev)
     args = [d(a) for a in (g.x, g.y, g.flux, g.r_e, g.e1, g.e2)]
-    go = torch.randn((len(g), 64, 64), device=dev, generator=torch.Generator(device=dev).manual_seed(5))
+    go = d(wl.generate.noise_field(BWD_NOISE_SEED, len(g), 64))
     ws = torch.empty(gfc.gfc_backward_workspace_bytes(len(g)) // 4 + 1, dtype=torch.float32, device=dev)
     gp = torch.empty((len(g), 6), dtype=torch.float32, device=dev)
     ga = torch.zeros((1, 16), dtype=torch.float32, device=dev)
-    gfc.gfc_render_stamps_backward(ctx, psf, mix, *args, 64, go, grad_params=gp, grad_amp=ga, workspace=ws)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        gfc.gfc_render_stamps_backward(ctx, psf, mix, *args, 64, go, grad_params=gp, grad_amp=ga, workspace=ws)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    res["backward-dev8-64x64-10k"] = dict(stamps=len(g), ms=round(ms, 4), stamps_per_s=round(len(g) / ms * 1e3, 1))
+    ms = timed(lambda: gfc.gfc_render_stamps_backward(ctx, psf, mix, *args, 64, go, grad_params=gp, grad_amp=ga,
+                                                      workspace=ws), reps)
+    par = None
+    if "backward" in refs:
+        ii, ref = refs["backward"]
+        got = gp[torch.as_tensor(ii, device=dev)].cpu().numpy().astype(np.float64)
+        ref = np.stack(ref)
+        rms = np.sqrt(np.mean(ref**2, axis=0, keepdims=True))
+        big = np.abs(ref) >= 1e-2 * rms
+        bound = 1e-4 * np.abs(ref) + np.where(big, 0.0, 1e-5 * rms)
+        rel = np.where(big, np.abs(got - ref) / np.maximum(np.abs(ref), 1e-300), 0.0)
+        par = dict(n_checked=int(len(ii)), max_rel_err=float(rel.max()), max_err_over_bound=float(
+            (np.abs(got - ref) / bound).max()), tol="1e-4 relative where |oracle| >= 1e-2 rms, else + 1e-5 rms",
+                   passed=bool((np.abs(got - ref) <= bound).all()))
+    res["backward-dev8-64x64-10k"] = line(len(g), ms, parity=par)
     psf.close()
     mix.close()
     return res
 
 
-def plain_per_request(gfc, ctx, psf, mix, gal, W, dev, seed=77):
+def plain_per_request(gfc, ctx, psf, mix, gal, W, dev, refs, seed=77):
     """The plain alternative to one batched launch: the same stamps split into
     requests of log-uniform 1..4096 galaxies, each with its own host-to-device
-    parameter copy and its own launch, FIFO on one stream."""
+    parameter copy and its own launch, FIFO on one stream.  Parity: the
+    stamps of the CPU leg's sample, from this run's output."""
     import torch
 
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -483,7 +766,7 @@ def plain_per_request(gfc, ctx, psf, mix, gal, W, dev, seed=77):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     return dict(value=round(n / dt, 1), unit="stamps/s", requests=len(sizes),
-                mean_request=round(n / len(sizes), 1),
+                mean_request=round(n / len(sizes), 1), parity=parity_of_rows(out, refs, dev),
                 note="one launch per request incl. its H2D parameter copy, FIFO on one stream")
 
 

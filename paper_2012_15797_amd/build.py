@@ -22,6 +22,9 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB_NAME = "libgfc.so"
 LIB_PATH = os.path.join(PKG_DIR, LIB_NAME)
+# rate probes for the roofline denominators (include/gfc_microbench.h)
+MB_LIB_PATH = os.path.join(PKG_DIR, "libgfc_microbench.so")
+MB_SOURCES = ["microbench.hip"]
 ARCH = "gfx950"
 
 SOURCES = [
@@ -60,26 +63,32 @@ def _compile(src: str, obj: str) -> None:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
 
 
-def build_library(verbose: bool = False, jobs: int = 8) -> str:
-    """Generates the twiddle table, compiles every source and links libgfc.so.
-    Always rebuilds.  Returns the library path."""
-    os.makedirs(BUILD_DIR, exist_ok=True)
-    subprocess.run([sys.executable, os.path.join(CSRC, "gen_twiddles.py"),
-                    os.path.join(CSRC, "twiddles.inc")], check=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    objs = [os.path.join(BUILD_DIR, os.path.splitext(s)[0] + ".o") for s in srcs]
-    with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
-        futs = [ex.submit(_compile, os.path.join(CSRC, s), o) for s, o in zip(srcs, objs)]
-        for f in futs:
-            f.result()
-    tmp = LIB_PATH + ".tmp"
+def _link(objs, path):
+    tmp = path + ".tmp"
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB_PATH)
+    os.replace(tmp, path)
+
+
+def build_library(verbose: bool = False, jobs: int = 8) -> str:
+    """Generates the twiddle table, compiles every source and links libgfc.so
+    and the rate-probe library libgfc_microbench.so.  Always rebuilds.
+    Returns the path of libgfc.so."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    subprocess.run([sys.executable, os.path.join(CSRC, "gen_twiddles.py"),
+                    os.path.join(CSRC, "twiddles.inc")], check=True)
+    srcs = [s for s in SOURCES + MB_SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    objs = {s: os.path.join(BUILD_DIR, os.path.splitext(s)[0] + ".o") for s in srcs}
+    with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
+        futs = [ex.submit(_compile, os.path.join(CSRC, s), o) for s, o in objs.items()]
+        for f in futs:
+            f.result()
+    _link([objs[s] for s in SOURCES], LIB_PATH)
+    _link([objs[s] for s in MB_SOURCES], MB_LIB_PATH)
     if verbose:
-        print(f"built {LIB_PATH} from {len(srcs)} sources")
+        print(f"built {LIB_PATH} from {len(SOURCES)} sources and {MB_LIB_PATH}")
     return LIB_PATH
 
 

@@ -43,3 +43,18 @@ def test_host_only_calls_work_without_a_gpu():
     assert lib.gfc_stamp_size_supported(64) == 1 and lib.gfc_stamp_size_supported(48) == 0
     assert lib.gfc_status_str(-6) == b"rejected"
     assert lib.gfc_backward_workspace_bytes(10) >= 10 * 16 * 4
+
+
+def test_rate_probe_library_exports_its_header():
+    """libgfc_microbench.so (the roofline denominators' probes) exports every
+    function include/gfc_microbench.h declares."""
+    import ctypes
+
+    text = open(os.path.join(ROOT, "include", "gfc_microbench.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = sorted(set(re.findall(r"^int\s+(gfc_mb_\w+)\s*\(", text, flags=re.M)))
+    assert names == ["gfc_mb_exp", "gfc_mb_exp_fma", "gfc_mb_fma", "gfc_mb_hbm_copy", "gfc_mb_hbm_write"]
+    import paper_2012_15797_amd  # noqa: F401  (torch's HIP runtime first)
+
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2012_15797_amd", "libgfc_microbench.so"))
+    assert all(hasattr(lib, n) for n in names)
