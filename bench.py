@@ -134,6 +134,26 @@ REF_JOBS = {
 BWD_NOISE_SEED = wl.SEED_BASE + 55    # upstream gradient of the adjoint line: unit-normal noise
 
 
+def serving_traces(seconds):
+    """(label, rate, seconds, restricted) of the replayed traces: the full
+    serving configuration (64 PSFs, stamps 16..256) and the 64x64 one-PSF
+    variant at the nominal and a saturating rate."""
+    return (("", 2000.0, seconds, False), ("restricted64_", 2000.0, min(seconds, 3.0), True),
+            ("saturated64_", 20000.0, min(seconds, 1.0), True))
+
+
+def serving_sample(requests):
+    """Requests whose stamps gate a replay: per stamp size, two seeded
+    requests of at most 256 galaxies, and their first three galaxies."""
+    rng = np.random.Generator(np.random.PCG64(7100))
+    out = []
+    for W in sorted({r["W"] for r in requests}):
+        cand = [i for i, r in enumerate(requests) if r["W"] == W and len(r["gal"]) <= 256]
+        for i in sorted(rng.choice(cand, min(2, len(cand)), replace=False).tolist()):
+            out.append((i, list(range(min(3, len(requests[i]["gal"]))))))
+    return out
+
+
 def ref_indices(job, n_total, k):
     """Seeded sample of a workload; for the mixed and large workloads it is
     stratified by stamp size (equal numbers per size)."""
@@ -149,8 +169,9 @@ def ref_indices(job, n_total, k):
     return np.sort(rng.choice(n_total, k, replace=False))
 
 
-def _oracle_job(job, idx, n_metric):
-    """The oracle's stamps (or gradients) for one reference job."""
+def _oracle_job(job, idx, n_metric, serve_spec=None):
+    """The oracle's stamps (or gradients) for one reference job; a serving
+    job returns the stamps of its trace's sample in order (idx numbers them)."""
     import oracle as o
     from oracle import eigen as oe
     from oracle import lanczos as ol
@@ -208,6 +229,21 @@ def _oracle_job(job, idx, n_metric):
             lg = o.loss_gradient(noise[i].astype(np.float64), J)
             out.append(np.array([lg[k] for k in ("x", "y", "flux", "log_re", "e1", "e2")]))
         return out
+    if job.startswith("serving"):
+        label, rate, secs, restricted = serve_spec[job]
+        tr = wl.config4_trace(duration_s=secs, rate_hz=rate, restricted=restricted)
+        m = tr["mix"].as_f32()
+        out = []
+        for ri, gis in serving_sample(tr["requests"]):
+            r = tr["requests"][ri]
+            P = np.asarray(tr["psfs"][r["psf"]], np.float32).astype(np.float64)
+            ph, g = o.psf_spectrum(P, r["W"]), o.psf_gauss_moments(P)
+            for gi in gis:
+                p = r["gal"].params(gi)
+                amp, var = m.table(p["mix_id"])
+                out.append(o.render_stamp(ph, g, amp, var, p["x"], p["y"], p["flux"], p["r_e"], p["e1"], p["e2"],
+                                          r["W"]))
+        return out
     raise ValueError(job)
 
 
@@ -221,9 +257,10 @@ def oracle_worker_main():
     with threadpoolctl.threadpool_limits(1):
         for job, idx, timed in spec["jobs"]:
             t0 = time.perf_counter()
-            out = _oracle_job(job, [int(i) for i in idx], spec["n_metric"])
+            out = _oracle_job(job, [int(i) for i in idx], spec["n_metric"], spec.get("serve"))
             dt = time.perf_counter() - t0
-            for i, a in zip(idx, out):
+            keys = range(len(out)) if job.startswith("serving") else idx   # a serving job numbers its stamps
+            for i, a in zip(keys, out):
                 res[f"{job}/{i}"] = np.asarray(a, np.float64)
             if timed:
                 res[f"__cpu_s__/{job}/{idx[0]}"] = np.array(dt)
@@ -233,7 +270,7 @@ def oracle_worker_main():
     sys.stdout.buffer.flush()
 
 
-def _run_workers(job_lists, n_metric):
+def _run_workers(job_lists, n_metric, serve=None):
     """One child process per job list; returns (merged results, wall s).
     Every child is waited for, so none outlives the call."""
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
@@ -246,7 +283,7 @@ def _run_workers(job_lists, n_metric):
     outs = []
     try:
         for p, jobs in zip(procs, job_lists):
-            p.stdin.write(json.dumps(dict(jobs=jobs, n_metric=n_metric)).encode())
+            p.stdin.write(json.dumps(dict(jobs=jobs, n_metric=n_metric, serve=serve)).encode())
             p.stdin.close()
         for p in procs:
             data = p.stdout.read()
@@ -268,7 +305,7 @@ def _run_workers(job_lists, n_metric):
     return merged, wall
 
 
-def cpu_leg(n_metric, sample, workers, other):
+def cpu_leg(n_metric, sample, workers, other, serve_seconds=0.0):
     """The oracle, unchanged, timed on a seeded sample of the metric workload
     in `workers` single-threaded processes (cpu_baseline); then the untimed
     reference samples of the other numbers.  Runs before the GPU is touched."""
@@ -288,9 +325,11 @@ def cpu_leg(n_metric, sample, workers, other):
                       f"of which a one-GPU box grants {CPU_SHARE}); {cpu_s:.1f} CPU-s, the slowest process "
                       f"{span:.2f} s in the oracle (value = sample / that), {wall:.2f} s wall with start-up")
     refs = {}
-    if other:
-        jobs = []
-        for job, k in REF_JOBS.items():
+    serve = {f"serving_{label or 'full_'}": [label, rate, secs, restricted]
+             for label, rate, secs, restricted in serving_traces(serve_seconds)} if serve_seconds > 0 else {}
+    if other or serve:
+        jobs = [[job, [0], False] for job in serve]   # one job per trace (it draws the whole trace)
+        for job, k in (REF_JOBS.items() if other else ()):
             n_total = {"lanczos": 100_000, "sersic": 100_000, "composite": 100_000, "eigen": 100_000,
                        "backward": 10_000}.get(job, 0)
             ii = ref_indices(job, n_total, k)
@@ -299,8 +338,11 @@ def cpu_leg(n_metric, sample, workers, other):
                 if len(c):
                     jobs.append([job, c.tolist(), False])
         lists = [jobs[i::workers] for i in range(workers) if jobs[i::workers]]
-        res2, wall2 = _run_workers(lists, n_metric)
+        res2, wall2 = _run_workers(lists, n_metric, serve)
         refs = {job: (ii, [res2[f"{job}/{i}"] for i in ii]) for job, ii in refs.items()}
+        for job in serve:   # a serving job's stamps come back numbered 0, 1, ...
+            k = sum(1 for key in res2 if key.startswith(job + "/"))
+            refs[job] = [res2[f"{job}/{i}"] for i in range(k)]
         log(f"cpu leg: reference samples for {len(refs)} workloads in {wall2:.1f} s")
     return cpu, metric_refs, refs
 
@@ -407,7 +449,7 @@ def main():
         share = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
         workers = args.cpu_workers or max(1, min(CPU_SHARE, share))
         log(f"cpu leg: oracle on {args.cpu_sample} stamps with {workers} processes")
-        cpu, oracle_stamps, refs = cpu_leg(args.n, args.cpu_sample, workers, not args.no_other)
+        cpu, oracle_stamps, refs = cpu_leg(args.n, args.cpu_sample, workers, not args.no_other, args.serve_seconds)
         log(f"cpu baseline: {cpu['value']:.1f} stamps/s")
 
     import torch
@@ -461,7 +503,7 @@ def main():
     roofline = dict(bound="alu", achieved=round(achieved_tflops, 3), peak=round(FP32_FMA_NONPACKED_TFLOPS, 2),
                     unit="TFLOP/s", frac=round(achieved_tflops / FP32_FMA_NONPACKED_TFLOPS, 4),
                     traffic=measured_traffic(),
-                    kernel="render_small_kernel<64, false, false>",
+                    kernel="render_small_kernel<64, false, false, false>",
                     flops_per_stamp=round(float(flops_stamp.mean()), 1),
                     peak_note="FP32 vector FMA peak without packed instructions: 256 CU x 4 SIMD x 16 lanes x "
                               "2 FLOP x 2.4 GHz",
@@ -503,7 +545,7 @@ def main():
 
     serving = None
     if args.serve_seconds > 0:
-        serving = serving_benchmark(gfc, ctx, args.serve_seconds)
+        serving = serving_benchmark(gfc, ctx, args.serve_seconds, refs)
 
     other = None
     if not args.no_other:
@@ -547,19 +589,20 @@ def parity_of_rows(out, refs, dev):
     return stamp_parity(rows, [refs[i] for i in idx])
 
 
-def serving_benchmark(gfc, ctx, seconds):
+def serving_benchmark(gfc, ctx, seconds, refs):
     """Open-loop replays of Poisson request traces against the
     continuous-batching server and against the plain mode (one launch per
     request, FIFO on one stream), with the same 32 GB device-memory budget:
     the full serving configuration (2,000 requests/s for `seconds`, 64
     resident PSFs, stamps 16..256), and the 64x64 one-PSF variant at the
-    nominal and a saturating rate."""
+    nominal and a saturating rate.  Each replay keeps the stamps of a seeded
+    sample of its requests, checked against the CPU leg's oracle."""
+    import torch
+
     from paper_2012_15797_amd.serving import Server, replay_trace
 
     out = {}
-    for label, rate, secs, restricted in (("", 2000.0, seconds, False),
-                                          ("restricted64_", 2000.0, min(seconds, 3.0), True),
-                                          ("saturated64_", 20000.0, min(seconds, 1.0), True)):
+    for label, rate, secs, restricted in serving_traces(seconds):
         t0 = time.perf_counter()
         tr = wl.config4_trace(duration_s=secs, rate_hz=rate, restricted=restricted)
         log(f"serving trace {label or 'full_'}: {len(tr['requests'])} requests drawn in "
@@ -573,10 +616,18 @@ def serving_benchmark(gfc, ctx, seconds):
                 "stamp sizes 16..256, EXP6/DEV8, 64 PSFs")
         out[label + "trace"] = (f"{len(tr['requests'])} requests over {secs:.1f} s, Poisson {rate:.0f}/s, "
                                 f"1..4096 galaxies log-uniform, {what}, budget 32 GB")
+        sample = serving_sample(tr["requests"])
+        ref = refs.get(f"serving_{label or 'full_'}")
         for name, streams, max_batch in (("batched", 2, 1 << 16), ("plain", 1, 0)):
+            keep = {ri: torch.empty((len(tr["requests"][ri]["gal"]), tr["requests"][ri]["W"], tr["requests"][ri]["W"]),
+                                    dtype=torch.float32, device=ctx.torch_device) for ri, _ in sample}
             srv = Server(ctx, mem_budget_bytes=32 << 30, n_streams=streams, max_batch_stamps=max_batch)
-            out[label + name] = replay_trace(srv, tr["requests"], psfs, mix)
+            out[label + name] = replay_trace(srv, tr["requests"], psfs, mix, keep=keep)
             srv.close()
+            if ref is not None:
+                rows = [keep[ri][gi].cpu().numpy().astype(np.float64) for ri, gis in sample for gi in gis]
+                out[label + name]["parity"] = stamp_parity(rows, ref)
+            del keep
             log(f"serving {label or 'full_'}{name}: {out[label + name]}")
         for p in psfs:
             p.close()

@@ -283,17 +283,27 @@ typedef struct {
 } gfc_request;
 
 /* mem_budget_bytes: device bytes the server may hold for admitted requests
- * (outputs + parameters: n * (4 W^2 + 28) bytes each); max_batch_stamps:
- * most stamps fused into one launch (<= 0: one launch per request, the plain
- * mode); n_streams: concurrent launch streams (1..8).  The policy is that of
- * the scheduling core below.  A background thread launches and reaps.  The
- * server reserves its budget (at most 80% of the device's free memory) as one
- * device allocation at creation and places batches in it; when that is
- * fragmented a batch takes a stream-ordered allocation instead. */
+ * (outputs + parameters: n * (4 W^2 + 32) bytes each, rounded up to 256);
+ * max_batch_stamps: most stamps fused into one launch (<= 0: one launch per
+ * request, the plain mode); n_streams: concurrent launch streams (1..8).  The
+ * policy is that of the scheduling core below, with the key (mixture, stamp
+ * size, flags): requests with different PSFs share a launch, each galaxy
+ * reading its own request's PSF (steps 1-2: the transform of a PSF is made
+ * once and kept).  The first request naming a PSF at a stamp size enters
+ * that PSF's cached spectrum (filled then, if gfc_psf_prepare has not) and
+ * its Gaussian in the server's device tables, on the submitting thread; a
+ * server holds at most 65,536 PSFs, and a PSF must outlive the requests
+ * naming it.  A background thread launches and reaps; it never fills a
+ * cache.  The server reserves its budget (at most 80% of the device's free
+ * memory) as one device allocation at creation and places batches in it;
+ * when that is fragmented a batch takes a stream-ordered allocation
+ * instead. */
 gfc_status gfc_server_create(gfc_ctx* ctx, size_t mem_budget_bytes, int n_streams,
                              int64_t max_batch_stamps, gfc_server** out);
-/* Queues a request; returns at once with a ticket.  GFC_EREJECTED if the
- * request alone exceeds the budget, GFC_EINVAL for a malformed request. */
+/* Queues a request; returns with a ticket once its parameters are copied
+ * (and, the first time its PSF is seen at its stamp size, the PSF entered).
+ * GFC_EREJECTED if the request alone exceeds the budget, GFC_EINVAL for a
+ * malformed request. */
 gfc_status gfc_server_submit(gfc_server* srv, const gfc_request* req, uint64_t* ticket);
 /* done = 1 once the stamps are complete in device memory; out_dev then
  * points at [n][W][W] float32 (valid until release).  status_out (may be
@@ -324,12 +334,15 @@ gfc_status gfc_server_stats(gfc_server* srv, double* p50_ms, double* p99_ms, dou
  * every submitted request is released.  t_arrive: host, n doubles, finite,
  * non-negative, non-decreasing.  lag: host, n doubles receiving how late
  * each submission was (seconds), or NULL.  span_s: seconds from t0 to the
- * last completion, or NULL.  Latencies are then in gfc_server_stats.  A
- * rejected submission stops the replay (GFC_EREJECTED after draining); a
- * failed request gives its status.  Not to be called concurrently with
- * other submissions to the same server. */
+ * last completion, or NULL.  keep: host array of n device pointers, or
+ * NULL: request i's stamps (n_i W^2 float32) are copied to keep[i], when it
+ * is not NULL, before the request is released (the replay waits for those
+ * copies before it returns), so a caller can check a sample of the run.
+ * Latencies are then in gfc_server_stats.  A rejected submission stops the
+ * replay (GFC_EREJECTED after draining); a failed request gives its status.
+ * Not to be called concurrently with other submissions to the same server. */
 gfc_status gfc_server_replay(gfc_server* srv, const gfc_request* reqs, const double* t_arrive,
-                             int64_t n, double* lag, double* span_s);
+                             int64_t n, float* const* keep, double* lag, double* span_s);
 /* Drains every queued request, then frees the server. */
 gfc_status gfc_server_destroy(gfc_server* srv);
 
@@ -337,7 +350,7 @@ gfc_status gfc_server_destroy(gfc_server* srv);
 /* The server's scheduler with the device replaced by caller callbacks, for
  * driving and testing the policy without a GPU: strict-FIFO admission
  * against the memory budget, batches of admitted requests that share a key
- * (PSF, mixture, stamp size, flags) formed oldest-first up to
+ * (the server's is mixture, stamp size and flags) formed oldest-first up to
  * max_batch_stamps (<= 0: one request per launch, the plain mode), at most
  * one batch in flight per stream, latency = completion - submit on the
  * callbacks' clock.  Nothing runs in the background: each gfc_sched_step()

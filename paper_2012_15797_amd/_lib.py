@@ -100,8 +100,8 @@ PROTOTYPES = {
     "gfc_server_release": (I32, [P, U64]),
     "gfc_server_stats": (I32, [P, ctypes.POINTER(D), ctypes.POINTER(D), ctypes.POINTER(D),
                                ctypes.POINTER(D), ctypes.POINTER(U64), ctypes.POINTER(U64)]),
-    "gfc_server_replay": (I32, [P, ctypes.POINTER(gfc_request), ctypes.POINTER(D), I64, ctypes.POINTER(D),
-                                ctypes.POINTER(D)]),
+    "gfc_server_replay": (I32, [P, ctypes.POINTER(gfc_request), ctypes.POINTER(D), I64, ctypes.POINTER(P),
+                                ctypes.POINTER(D), ctypes.POINTER(D)]),
     "gfc_server_destroy": (I32, [P]),
     "gfc_sched_create": (I32, [ctypes.c_void_p, ctypes.c_size_t, I32, I64, PP]),
     "gfc_sched_submit": (I32, [P, U64, I64, ctypes.c_size_t, ctypes.POINTER(U64)]),

@@ -48,6 +48,14 @@ struct RenderArgs {
   float eig_norm[4];        // x_off, 1 / x_scale, y_off, 1 / y_scale
   const float* psf_px;      // [n] image position of each galaxy (eigen PSF only)
   const float* psf_py;
+  // Stamps of several constant PSFs in one launch (serving): galaxy i uses
+  // PSF psf_id[i] of these tables instead of psf_main / psf_nyq / pg.  An
+  // index outside [0, n_psf) makes the galaxy invalid.  Null psf_id: one PSF.
+  const int32_t* psf_id;              // [n]
+  const float2* const* psf_main_tab;  // [n_psf] spectra for this W, laid out as psf_main
+  const float2* const* psf_nyq_tab;   // [n_psf] Nyquist columns
+  const float* pg_tab;                // [n_psf][6] PSF Gaussians
+  int n_psf;
 };
 
 constexpr int kEigMax = 16;     // eigen-PSF components

@@ -81,6 +81,11 @@ gfc_status psf_cache(gfc_psf* psf, int W, hipStream_t stream, const PsfSpectrum*
   return GFC_OK;
 }
 
+uint64_t next_psf_uid() {
+  static std::atomic<uint64_t> next{1};
+  return next.fetch_add(1);
+}
+
 const PsfSpectrum* psf_cache_find(gfc_psf* psf, int W) {
   std::lock_guard<std::mutex> lock(psf->mu);
   const auto it = psf->cache.find(W);
@@ -294,6 +299,7 @@ static gfc_status psf_create_impl(gfc_ctx* ctx, const double* pix, int Sy, int S
   auto* psf = new (std::nothrow) gfc_psf();
   if (!psf) return fail(GFC_ENOMEM, "PSF allocation failed");
   psf->ctx = ctx;
+  psf->uid = next_psf_uid();
   psf->Sy = Sy;
   psf->Sx = Sx;
   std::memcpy(psf->gauss, g, sizeof(g));
@@ -369,6 +375,7 @@ gfc_status gfc_psf_create_eigen(gfc_ctx* ctx, const float* comps, int J, int Sy,
   auto* psf = new (std::nothrow) gfc_psf();
   if (!psf) return fail(GFC_ENOMEM, "PSF allocation failed");
   psf->ctx = ctx;
+  psf->uid = next_psf_uid();
   psf->Sy = Sy;
   psf->Sx = Sx;
   psf->J = J;

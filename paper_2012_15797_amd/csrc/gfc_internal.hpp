@@ -31,6 +31,7 @@ struct PsfSpectrum {
 
 struct gfc_psf {
   gfc_ctx* ctx = nullptr;
+  uint64_t uid = 0;  // unique in the process (a later PSF at the same address has another)
   int Sy = 0, Sx = 0;
   double* d_pix = nullptr;  // device, float64 [J or 1][Sy][Sx]
   double gauss[6] = {0, 0, 0, 0, 0, 0};
@@ -71,6 +72,8 @@ class DeviceGuard {
 };
 
 gfc_status psf_cache(gfc_psf* psf, int W, hipStream_t stream, const PsfSpectrum** out);
+// Next process-unique PSF id.
+uint64_t next_psf_uid();
 // The cached spectrum for W, or nullptr when it has not been filled (never fills).
 const PsfSpectrum* psf_cache_find(gfc_psf* psf, int W);
 // Takes the device address of the allocation-free adjoint's scratch array on

@@ -47,7 +47,10 @@ struct SmallCfg {
 // W = 128 is held to two wavefronts per SIMD (a small spill costs less than
 // running one wavefront per SIMD); the other sizes reach their occupancy freely.
 // LZ (W <= 64): the Lanczos-3 sub-pixel shift is applied while storing.
-template <int W, bool EIG, bool LZ>
+// PT: each galaxy names its (constant) PSF in p.psf_id, and the stamp takes
+// that PSF's spectrum and Gaussian from the tables (a serving batch mixes
+// PSFs); the one-PSF instantiations compile exactly as without it.
+template <int W, bool EIG, bool LZ, bool PT>
 __global__ void __launch_bounds__((SmallCfg<W, EIG>::BLOCK)) __attribute__((amdgpu_waves_per_eu(W == 128 ? 2 : 1)))
 render_small_kernel(RenderArgs p) {
   using C = SmallCfg<W, EIG>;
@@ -67,6 +70,23 @@ render_small_kernel(RenderArgs p) {
   Galaxy G = load_galaxy<W>(p, live ? stamp : p.n - 1);
   if constexpr (C::WAVE1) {  // one stamp per wavefront: keep its integer shift in SGPRs
     make_uniform(G);
+  }
+  // This stamp's PSF spectrum (lane-permuted main columns, Nyquist column)
+  // and the index of its Gaussian in the table (PT).
+  const float2* psfm = p.psf_main;
+  const float2* psfn = p.psf_nyq;
+  int ps = 0;
+  if constexpr (PT) {
+    static_assert(!EIG, "a per-galaxy PSF index takes constant PSFs");
+    ps = p.psf_id[live ? stamp : p.n - 1];
+    if constexpr (C::WAVE1) ps = __builtin_amdgcn_readfirstlane(ps);
+    if (ps < 0 || ps >= p.n_psf) {  // invalid galaxy: NaN stamp, counted
+      ps = 0;
+      G.ok = false;
+      G.flux = __builtin_nanf("");
+    }
+    psfm = p.psf_main_tab[ps];
+    psfn = p.psf_nyq_tab[ps];
   }
   // Lanczos-3 weights of the fused shift (taps d = -3..2 along x, then y),
   // formed up front: with one stamp per wavefront they sit in scalar
@@ -259,11 +279,15 @@ render_small_kernel(RenderArgs p) {
       if constexpr (!kPsfStream) {
         static_for<0, M>([&](auto mm) {
           constexpr int m = decltype(mm)::value;
-          Pm[m] = p.psf_main[m * W + l];
+          Pm[m] = psfm[m * W + l];
         });
       }
-      psfN = p.psf_nyq[l];
-      static_for<0, 6>([&](auto ii) { pg[decltype(ii)::value] = p.pg[decltype(ii)::value]; });
+      psfN = psfn[l];
+      if constexpr (PT) {
+        static_for<0, 6>([&](auto ii) { pg[decltype(ii)::value] = p.pg_tab[6 * ps + decltype(ii)::value]; });
+      } else {
+        static_for<0, 6>([&](auto ii) { pg[decltype(ii)::value] = p.pg[decltype(ii)::value]; });
+      }
     }
   };
   if constexpr (kPsfFirst) psf_terms();
@@ -382,7 +406,7 @@ render_small_kernel(RenderArgs p) {
   static_for<0, M>([&](auto mm) {
     constexpr int m = decltype(mm)::value;
     float2 P;
-    if constexpr (kPsfStream) P = p.psf_main[m * W + l];
+    if constexpr (kPsfStream) P = psfm[m * W + l];
     else P = Pm[m];
     if constexpr (2 * m == W / 2) {
       const float2 q0 = s_py[slot][W / 2 + h];
@@ -621,7 +645,7 @@ render_small_kernel(RenderArgs p) {
   if (live && !G.ok && l == 0) atomicAdd(p.invalid, 1ull);
 }
 
-template <int W, bool EIG, bool LZ>
+template <int W, bool EIG, bool LZ, bool PT>
 static hipError_t launch_small(const RenderArgs& args, hipStream_t stream) {
   using C = SmallCfg<W, EIG>;
   constexpr int64_t kMaxBlocks = 1 << 30;
@@ -639,9 +663,10 @@ static hipError_t launch_small(const RenderArgs& args, hipStream_t stream) {
     p.out = args.out + done * (int64_t)W * W;
     p.psf_px = args.psf_px ? args.psf_px + done : nullptr;
     p.psf_py = args.psf_py ? args.psf_py + done : nullptr;
+    p.psf_id = args.psf_id ? args.psf_id + done : nullptr;
     p.n = chunk;
     const unsigned blocks = (unsigned)((chunk + C::SPB - 1) / C::SPB);
-    hipLaunchKernelGGL((render_small_kernel<W, EIG, LZ>), dim3(blocks), dim3(C::BLOCK), 0, stream, p);
+    hipLaunchKernelGGL((render_small_kernel<W, EIG, LZ, PT>), dim3(blocks), dim3(C::BLOCK), 0, stream, p);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     done += chunk;
@@ -651,11 +676,21 @@ static hipError_t launch_small(const RenderArgs& args, hipStream_t stream) {
 
 template <int W>
 hipError_t launch_render_small(const RenderArgs& args, hipStream_t stream) {
-  if constexpr (W <= 64) {
-    if (args.flags & kLanczos3)
-      return args.eig_J > 0 ? launch_small<W, true, true>(args, stream) : launch_small<W, false, true>(args, stream);
+  const bool lz = (W <= 64) && (args.flags & kLanczos3);
+  if (args.psf_id) {  // per-galaxy constant PSFs (eig_J == 0)
+    if (args.eig_J > 0) return hipErrorInvalidValue;
+    if constexpr (W <= 64) {
+      if (lz) return launch_small<W, false, true, true>(args, stream);
+    }
+    return launch_small<W, false, false, true>(args, stream);
   }
-  return args.eig_J > 0 ? launch_small<W, true, false>(args, stream) : launch_small<W, false, false>(args, stream);
+  if constexpr (W <= 64) {
+    if (lz)
+      return args.eig_J > 0 ? launch_small<W, true, true, false>(args, stream)
+                            : launch_small<W, false, true, false>(args, stream);
+  }
+  return args.eig_J > 0 ? launch_small<W, true, false, false>(args, stream)
+                        : launch_small<W, false, false, false>(args, stream);
 }
 
 template hipError_t launch_render_small<16>(const RenderArgs&, hipStream_t);

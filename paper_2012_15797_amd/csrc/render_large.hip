@@ -70,7 +70,8 @@ __device__ __forceinline__ int psf_index(int m, int l) {
 }
 
 // EIG: spatially varying PSF (eigen-PSF components with polynomial weights).
-template <int W, bool EIG>
+// PT: each galaxy names its constant PSF in p.psf_id (serving batches mix PSFs).
+template <int W, bool EIG, bool PT>
 __global__ void __launch_bounds__(LargeCfg<W>::BLOCK) __attribute__((amdgpu_waves_per_eu(2)))
 render_large_kernel(RenderArgs p, float2* __restrict__ scratch) {
   using C = LargeCfg<W>;
@@ -90,6 +91,20 @@ render_large_kernel(RenderArgs p, float2* __restrict__ scratch) {
     asm volatile("" : "+v"(t));
     Galaxy G = load_galaxy<W>(p, stamp);
     make_uniform(G);
+    const float2* psfm = p.psf_main;
+    const float2* psfn = p.psf_nyq;
+    int ps = 0;
+    if constexpr (PT) {
+      static_assert(!EIG, "a per-galaxy PSF index takes constant PSFs");
+      ps = __builtin_amdgcn_readfirstlane(p.psf_id[stamp]);
+      if (ps < 0 || ps >= p.n_psf) {  // invalid galaxy: NaN stamp, counted
+        ps = 0;
+        G.ok = false;
+        G.flux = __builtin_nanf("");
+      }
+      psfm = p.psf_main_tab[ps];
+      psfn = p.psf_nyq_tab[ps];
+    }
     const float* amp = p.amp + G.table * kKmax;
     const float* var = p.var + G.table * kKmax;
     const float trB = G.b11 + G.b22;
@@ -113,6 +128,8 @@ render_large_kernel(RenderArgs p, float2* __restrict__ scratch) {
         });
       }
       eigen_gauss(mom, pg);
+    } else if constexpr (PT) {
+      static_for<0, 6>([&](auto ii) { pg[decltype(ii)::value] = p.pg_tab[6 * ps + decltype(ii)::value]; });
     } else {
       static_for<0, 6>([&](auto ii) { pg[decltype(ii)::value] = p.pg[decltype(ii)::value]; });
     }
@@ -205,7 +222,7 @@ render_large_kernel(RenderArgs p, float2* __restrict__ scratch) {
             psfN = make_float2(fmaf(cj, qn2.x, psfN.x), fmaf(cj, qn2.y, psfN.y));
           }
         } else {
-          psfN = p.psf_nyq[t];
+          psfN = psfn[t];
         }
         float sy, cy, sxh, cxh;
         sincospi_poly(-2.f * G.fy * omN, &sy, &cy);
@@ -245,7 +262,7 @@ render_large_kernel(RenderArgs p, float2* __restrict__ scratch) {
             P = make_float2(fmaf(cj, q.x, P.x), fmaf(cj, q.y, P.y));
           }
         } else {
-          P = p.psf_main[psf_index<W>(m, l)];
+          P = psfm[psf_index<W>(m, l)];
         }
         if constexpr (D * m == W / 2) {
           const float2 q0 = s_py[W / 2 + h];
@@ -436,7 +453,7 @@ render_large_kernel(RenderArgs p, float2* __restrict__ scratch) {
 
 // Workgroups of one instantiation that stay resident at once (occupancy per
 // CU x CUs), queried once per instantiation.
-template <int W, bool EIG>
+template <int W, bool EIG, bool PT>
 static hipError_t large_resident(int64_t* out) {
   static int64_t cached = 0;
   if (cached == 0) {
@@ -444,7 +461,7 @@ static hipError_t large_resident(int64_t* out) {
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, render_large_kernel<W, EIG>, LargeCfg<W>::BLOCK, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, render_large_kernel<W, EIG, PT>, LargeCfg<W>::BLOCK, 0);
     if (e != hipSuccess) return e;
     cached = (int64_t)std::max(per, 1) * std::max(cus, 1);
   }
@@ -452,25 +469,26 @@ static hipError_t large_resident(int64_t* out) {
   return hipSuccess;
 }
 
-template <int W, bool EIG>
+template <int W, bool EIG, bool PT>
 static hipError_t launch_large(const RenderArgs& args, hipStream_t stream) {
   using C = LargeCfg<W>;
   // As many workgroups as stay resident, each with its own slab.
   int64_t resident = 0;
-  hipError_t e = large_resident<W, EIG>(&resident);
+  hipError_t e = large_resident<W, EIG, PT>(&resident);
   if (e != hipSuccess) return e;
   const int64_t nb = std::min<int64_t>(args.n, resident);
   float2* scratch = nullptr;
   e = hipMallocAsync((void**)&scratch, (size_t)nb * C::SLAB * sizeof(float2), stream);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((render_large_kernel<W, EIG>), dim3((unsigned)nb), dim3(C::BLOCK), 0, stream, args, scratch);
+  hipLaunchKernelGGL((render_large_kernel<W, EIG, PT>), dim3((unsigned)nb), dim3(C::BLOCK), 0, stream, args, scratch);
   e = hipGetLastError();
   hipError_t e2 = hipFreeAsync(scratch, stream);
   return e != hipSuccess ? e : e2;
 }
 
 hipError_t launch_render_w256(const RenderArgs& args, hipStream_t stream) {
-  return args.eig_J > 0 ? launch_large<256, true>(args, stream) : launch_large<256, false>(args, stream);
+  if (args.psf_id) return args.eig_J > 0 ? hipErrorInvalidValue : launch_large<256, false, true>(args, stream);
+  return args.eig_J > 0 ? launch_large<256, true, false>(args, stream) : launch_large<256, false, false>(args, stream);
 }
 
 }  // namespace gfc

@@ -5,10 +5,17 @@
 //   admission  strict FIFO: the oldest pending request is admitted when its
 //              bytes fit in what the budget has left; nothing behind it
 //              overtakes it (no starvation of large requests).
-//   batching   among admitted requests, the oldest one picks the key (PSF,
-//              mixture, stamp size, flags); later admitted requests with the
-//              same key join in arrival order up to max_batch_stamps.
+//   batching   among admitted requests, the oldest one picks the key
+//              (mixture, stamp size, flags), compared as that whole tuple;
+//              later admitted requests with the same key join in arrival
+//              order up to max_batch_stamps, whatever their PSFs: each galaxy
+//              of a batch carries the index of its request's PSF into the
+//              server's device tables of resident PSF spectra and Gaussians.
 //              max_batch_stamps <= 0 launches every request alone (plain).
+//   PSFs       the first request naming a PSF at a stamp size enters the
+//              PSF's cached spectrum for that size (filled then if needed)
+//              and its Gaussian in those tables, on the submitting thread:
+//              the launch thread never fills a cache.
 //   streams    at most one batch in flight per stream; requests arriving
 //              while every stream is busy are admitted and wait for the next
 //              free stream, where they are fused with whatever else arrived.
@@ -36,9 +43,16 @@
 namespace gfc {
 namespace serve {
 
+// Batching key, compared as a whole: (mixture, stamp size << 32 | flags) for
+// the server; (caller's key, 0) for the callback scheduler.
+struct BatchKey {
+  uint64_t a = 0, b = 0;
+  bool operator==(const BatchKey& o) const { return a == o.a && b == o.b; }
+};
+
 struct Req {
   uint64_t ticket = 0;
-  uint64_t key = 0;
+  BatchKey key;
   int64_t n = 0;
   size_t bytes = 0;
   int state = GFC_REQ_PENDING;
@@ -50,6 +64,7 @@ struct Req {
   const float* out_ptr = nullptr;  // device stamps once launched
   // payload used by the device executor
   gfc_psf* psf = nullptr;
+  int psf_slot = 0;               // index of the PSF in the server's device tables
   const gfc_mix* mix = nullptr;
   int W = 0;
   unsigned flags = 0;
@@ -59,7 +74,7 @@ struct Req {
 
 struct Batch {
   uint64_t id = 0;
-  uint64_t key = 0;
+  BatchKey key;
   int stream = -1;
   std::vector<Req*> reqs;
   int64_t n = 0;
@@ -145,7 +160,7 @@ class Core {
       for (auto it = admitted_.begin(); it != admitted_.end();) {
         Req* r = *it;
         const bool first = b->reqs.empty();
-        if (r->key != b->key) { ++it; continue; }
+        if (!(r->key == b->key)) { ++it; continue; }
         if (!first && (max_batch_ <= 0 || b->n + r->n > max_batch_)) break;
         r->offset = b->n;
         r->batch = b->id;
@@ -275,6 +290,20 @@ class HipExecutor : public Executor {
  public:
   HipExecutor(gfc_ctx* ctx, int n_streams, size_t budget) : ctx_(ctx) {
     DeviceGuard g(ctx_->device);
+    // Resident PSF tables: per stamp size, kPsfSlots spectrum pointers (main
+    // columns, Nyquist column), then kPsfSlots Gaussians [6].
+    const size_t ptrs = (size_t)kSizes * 2 * kPsfSlots;
+    void* t = nullptr;
+    if (hipMalloc(&t, ptrs * sizeof(void*) + (size_t)kPsfSlots * 6 * sizeof(float)) == hipSuccess) {
+      tables_ = t;
+      auto** base = static_cast<const float2**>(t);
+      for (int i = 0; i < kSizes; ++i) {
+        d_main_[i] = base + (size_t)(2 * i) * kPsfSlots;
+        d_nyq_[i] = base + (size_t)(2 * i + 1) * kPsfSlots;
+      }
+      d_pg_ = reinterpret_cast<float*>(base + ptrs);
+    }
+    hipStreamCreateWithFlags(&reg_stream_, hipStreamNonBlocking);
     streams_.resize(std::max(1, n_streams), nullptr);
     events_.resize(streams_.size(), nullptr);
     staging_.resize(streams_.size(), nullptr);
@@ -308,6 +337,8 @@ class HipExecutor : public Executor {
         hipEventDestroy(ev);
       }
     if (arena_) hipFree(arena_);
+    if (tables_) hipFree(tables_);
+    if (reg_stream_) hipStreamDestroy(reg_stream_);
     for (auto p : staging_)
       if (p) hipHostFree(p);
     for (auto e : events_)
@@ -316,13 +347,52 @@ class HipExecutor : public Executor {
   double now() override {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
   }
+  // The PSF's slot in the resident tables, entering it (and its spectrum for
+  // W) on first use.  Called on submitting threads, never under the server
+  // lock: filling a spectrum runs the PSF's DFT and waits for it.
+  gfc_status psf_slot(gfc_psf* psf, int W, int* slot_out) {
+    if (!tables_) return fail(GFC_ENOMEM, "the server's PSF tables could not be allocated");
+    std::lock_guard<std::mutex> lock(reg_mu_);
+    DeviceGuard g(ctx_->device);
+    int slot;
+    const auto it = slot_of_.find(psf->uid);
+    if (it == slot_of_.end()) {
+      slot = n_slots_.load();
+      if (slot >= kPsfSlots) return fail(GFC_EINVAL, "a server holds at most 65536 PSFs");
+      float pg[6];
+      for (int i = 0; i < 6; ++i) pg[i] = (float)psf->gauss[i];
+      hipError_t e = hipMemcpyAsync(d_pg_ + 6 * (size_t)slot, pg, sizeof(pg), hipMemcpyHostToDevice, reg_stream_);
+      if (e == hipSuccess) e = hipStreamSynchronize(reg_stream_);
+      if (e != hipSuccess) return hip_fail(e, "PSF table entry");
+      slot_of_[psf->uid] = slot;
+      filled_.push_back(0);
+      n_slots_.store(slot + 1);
+    } else {
+      slot = it->second;
+    }
+    const int wi = size_index(W);
+    if (!((filled_[(size_t)slot] >> wi) & 1u)) {
+      const PsfSpectrum* spec = nullptr;
+      const gfc_status st = psf_cache(psf, W, reg_stream_, &spec);
+      if (st != GFC_OK) return st;
+      hipError_t e = hipMemcpyAsync(d_main_[wi] + slot, &spec->main_cols, sizeof(void*), hipMemcpyHostToDevice,
+                                    reg_stream_);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(d_nyq_[wi] + slot, &spec->nyq_col, sizeof(void*), hipMemcpyHostToDevice, reg_stream_);
+      if (e == hipSuccess) e = hipStreamSynchronize(reg_stream_);  // the pointers are pageable stack values
+      if (e != hipSuccess) return hip_fail(e, "PSF table entry");
+      filled_[(size_t)slot] |= 1u << wi;
+    }
+    *slot_out = slot;
+    return GFC_OK;
+  }
   int launch(Batch& b) override {
     DeviceGuard g(ctx_->device);
     Req* r0 = b.reqs.front();
     const int W = r0->W;
     const int64_t n = b.n;
     const size_t out_bytes = (size_t)n * W * W * sizeof(float);
-    const size_t par_bytes = (size_t)n * (6 * sizeof(float) + sizeof(int32_t));
+    const size_t par_bytes = (size_t)n * (6 * sizeof(float) + 2 * sizeof(int32_t));  // params, mix_id, psf_id
     hipStream_t s = streams_[b.stream];
     // pinned staging for this stream (its previous batch has completed)
     if (staging_bytes_[b.stream] < par_bytes) {
@@ -334,6 +404,7 @@ class HipExecutor : public Executor {
     }
     float* hp = static_cast<float*>(staging_[b.stream]);
     int32_t* hm = reinterpret_cast<int32_t*>(hp + 6 * n);
+    int32_t* hs = hm + n;
     for (Req* r : b.reqs) {
       for (int f = 0; f < 6; ++f)
         std::memcpy(hp + f * n + r->offset, r->params.data() + f * r->n, r->n * sizeof(float));
@@ -341,6 +412,7 @@ class HipExecutor : public Executor {
         std::memset(hm + r->offset, 0, r->n * sizeof(int32_t));
       else
         std::memcpy(hm + r->offset, r->mix_id.data(), r->n * sizeof(int32_t));
+      std::fill(hs + r->offset, hs + r->offset + r->n, (int32_t)r->psf_slot);
     }
     b.arena_size = 0;
     if (void* m = arena_alloc(out_bytes + par_bytes, &b.arena_off)) {
@@ -354,8 +426,6 @@ class HipExecutor : public Executor {
     float* dout = static_cast<float*>(b.mem);
     float* dpar = reinterpret_cast<float*>(static_cast<char*>(b.mem) + out_bytes);
     if (hipMemcpyAsync(dpar, hp, par_bytes, hipMemcpyHostToDevice, s) != hipSuccess) return fail_batch(b);
-    const PsfSpectrum* spec = nullptr;
-    if (psf_cache(r0->psf, W, s, &spec) != GFC_OK) return fail_batch(b);
     gfc_galaxies gal{};
     gal.x = dpar;
     gal.y = dpar + n;
@@ -367,7 +437,13 @@ class HipExecutor : public Executor {
     gal.cd = nullptr;
     RenderArgs a;
     if (fill_render_args(ctx_, r0->psf, r0->mix, &gal, n, W, r0->flags, &a) != GFC_OK) return fail_batch(b);
-    attach_spectrum(&a, spec);
+    // each galaxy's PSF from the resident tables (its request's slot)
+    const int wi = size_index(W);
+    a.psf_id = reinterpret_cast<const int32_t*>(dpar + 7 * n);
+    a.psf_main_tab = d_main_[wi];
+    a.psf_nyq_tab = d_nyq_[wi];
+    a.pg_tab = d_pg_;
+    a.n_psf = n_slots_.load();
     a.out = dout;
     if (render_launch(a, W, s) != GFC_OK) return fail_batch(b);
     b.event = events_[b.stream];
@@ -411,6 +487,20 @@ class HipExecutor : public Executor {
     return -1;
   }
   gfc_ctx* ctx_;
+  // ---- resident PSFs (entries written on submitting threads under reg_mu_;
+  // the launch thread reads only n_slots_ and the device tables)
+  static constexpr int kPsfSlots = 65536;
+  static constexpr int kSizes = 5;  // W = 16, 32, 64, 128, 256
+  static int size_index(int W) { return __builtin_ctz((unsigned)W) - 4; }
+  void* tables_ = nullptr;
+  const float2** d_main_[kSizes] = {};
+  const float2** d_nyq_[kSizes] = {};
+  float* d_pg_ = nullptr;
+  hipStream_t reg_stream_ = nullptr;
+  std::mutex reg_mu_;
+  std::unordered_map<uint64_t, int> slot_of_;  // PSF uid -> slot
+  std::vector<uint8_t> filled_;                // per slot: bit i set once its spectrum for W = 16 << i is entered
+  std::atomic<int> n_slots_{0};
   std::vector<hipStream_t> streams_;
   std::vector<hipEvent_t> events_;
   std::vector<void*> staging_;
@@ -569,12 +659,16 @@ gfc_status gfc_server_submit(gfc_server* s, const gfc_request* q, uint64_t* tick
   r->psf = q->psf;
   r->mix = q->mix;
   r->flags = q->flags;
-  r->bytes = (size_t)q->n * ((size_t)q->W * q->W * sizeof(float) + 6 * sizeof(float) + sizeof(int32_t));
-  // batching key: PSF, mixture, stamp size, flags
-  uint64_t k = reinterpret_cast<uintptr_t>(q->psf);
-  k = k * 1000003u ^ reinterpret_cast<uintptr_t>(q->mix);
-  k = k * 1000003u ^ ((uint64_t)q->W << 8 | q->flags);
-  r->key = k;
+  // outputs and parameters (6 floats, mix_id, psf_id per galaxy), rounded up
+  // to the arena's 256-byte blocks so that a batch's block never exceeds the
+  // sum of its requests' charges
+  r->bytes = ((size_t)q->n * ((size_t)q->W * q->W * sizeof(float) + 6 * sizeof(float) + 2 * sizeof(int32_t)) +
+              255) & ~(size_t)255;
+  // batching key: mixture, stamp size, flags (PSFs mix within a batch)
+  r->key.a = reinterpret_cast<uintptr_t>(q->mix);
+  r->key.b = (uint64_t)q->W << 32 | q->flags;
+  const gfc_status pst = s->ex->psf_slot(q->psf, q->W, &r->psf_slot);
+  if (pst != GFC_OK) return pst;
   r->params.resize((size_t)6 * q->n);
   const float* src[6] = {q->x, q->y, q->flux, q->r_e, q->e1, q->e2};
   for (int f = 0; f < 6; ++f) std::memcpy(r->params.data() + (size_t)f * q->n, src[f], q->n * sizeof(float));
@@ -656,13 +750,20 @@ gfc_status gfc_server_stats(gfc_server* s, double* p50_ms, double* p99_ms, doubl
 }
 
 gfc_status gfc_server_replay(gfc_server* s, const gfc_request* reqs, const double* t_arrive, int64_t n,
-                             double* lag, double* span_s) {
+                             float* const* keep, double* lag, double* span_s) {
   if (!s || n < 0 || (n > 0 && (!reqs || !t_arrive))) return fail(GFC_EINVAL, "null argument or negative count");
   for (int64_t i = 0; i < n; ++i)
     if (!std::isfinite(t_arrive[i]) || t_arrive[i] < 0.0 || (i > 0 && t_arrive[i] < t_arrive[i - 1]))
       return fail(GFC_EINVAL, "arrival times must be finite, non-negative and non-decreasing");
   using clock = std::chrono::steady_clock;
   std::vector<uint64_t> tickets((size_t)n);
+  hipStream_t keep_stream = nullptr;  // copies of the kept requests' stamps
+  if (keep) {
+    DeviceGuard g(s->ctx->device);
+    const hipError_t e = hipStreamCreateWithFlags(&keep_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e, "replay copy stream");
+  }
+  gfc_status keep_st = GFC_OK;
   std::mutex m;
   std::condition_variable cv;
   int64_t submitted = 0;  // guarded by m
@@ -681,6 +782,10 @@ gfc_status gfc_server_replay(gfc_server* s, const gfc_request* reqs, const doubl
       const gfc_status st = gfc_server_wait(s, tickets[(size_t)i], -1, nullptr);
       if (st != GFC_OK && wait_st == GFC_OK) wait_st = st;
       t_last = std::chrono::duration<double>(clock::now() - t0).count();
+      if (st == GFC_OK && keep && keep[i]) {  // ordered before the block's reuse by the server
+        const gfc_status cs = gfc_server_copy(s, tickets[(size_t)i], keep[i], keep_stream);
+        if (cs != GFC_OK && keep_st == GFC_OK) keep_st = cs;
+      }
       gfc_server_release(s, tickets[(size_t)i]);
     }
   });
@@ -711,9 +816,16 @@ gfc_status gfc_server_replay(gfc_server* s, const gfc_request* reqs, const doubl
   }
   cv.notify_one();
   waiter.join();
+  if (keep_stream) {
+    DeviceGuard g(s->ctx->device);
+    const hipError_t e = hipStreamSynchronize(keep_stream);
+    hipStreamDestroy(keep_stream);
+    if (e != hipSuccess && keep_st == GFC_OK) keep_st = hip_fail(e, "replay copies");
+  }
   if (span_s) *span_s = t_last;
   if (sub_st != GFC_OK) return fail(sub_st, "a replayed request was not accepted");
   if (wait_st != GFC_OK) return fail(wait_st, "a replayed request failed");
+  if (keep_st != GFC_OK) return fail(keep_st, "a kept request's stamps could not be copied");
   return GFC_OK;
 }
 
@@ -749,7 +861,7 @@ gfc_status gfc_sched_create(const gfc_sched_executor* ex, size_t mem_budget_byte
 gfc_status gfc_sched_submit(gfc_sched* s, uint64_t key, int64_t n_stamps, size_t bytes, uint64_t* ticket) {
   if (!s || !ticket || n_stamps < 1) return fail(GFC_EINVAL, "bad argument");
   auto r = std::make_unique<Req>();
-  r->key = key;
+  r->key.a = key;
   r->n = n_stamps;
   r->bytes = bytes;
   return s->core->submit(std::move(r), ticket);

@@ -143,14 +143,16 @@ class Scheduler:
             self.handle = None
 
 
-def replay_trace(server, requests, psfs, mix, flags=0):
+def replay_trace(server, requests, psfs, mix, flags=0, keep=None):
     """Open-loop replay of a request trace (dicts with t [s], psf index, W,
     gal) against a server with the library's native load generator
     (gfc_server_replay): submissions at the arrival times and in-order
     waits and releases run on host threads of their own, so the Python
     interpreter does not pace the trace.  Returns server-side latency
     percentiles (submit to completion observed by the server), throughput
-    over the trace, and the submission lag behind the schedule."""
+    over the trace, and the submission lag behind the schedule.  keep:
+    {request index: device tensor [n, W, W]} receiving those requests'
+    stamps before their release."""
     n_req = len(requests)
     prepared = []
     stamps = 0
@@ -164,8 +166,13 @@ def replay_trace(server, requests, psfs, mix, flags=0):
     lag = np.zeros(n_req, np.float64)
     span = ctypes.c_double()
     D_p = ctypes.POINTER(ctypes.c_double)
-    call("gfc_server_replay", server.handle, reqs, t_arr.ctypes.data_as(D_p), n_req, lag.ctypes.data_as(D_p),
-         ctypes.byref(span))
+    keep_arr = None
+    if keep:
+        keep_arr = (ctypes.c_void_p * n_req)()
+        for i, t in keep.items():
+            keep_arr[i] = t.data_ptr()
+    call("gfc_server_replay", server.handle, reqs, t_arr.ctypes.data_as(D_p), n_req, keep_arr,
+         lag.ctypes.data_as(D_p), ctypes.byref(span))
     st = server.stats()
     return dict(requests=n_req, stamps=stamps, offered_rate_hz=n_req / max(requests[-1]["t"], 1e-9),
                 p50_ms=round(st["p50_ms"], 4), p99_ms=round(st["p99_ms"], 4), max_ms=round(st["max_ms"], 4),

@@ -58,6 +58,63 @@ def test_mixed_traffic_matches_direct_render(ctx):
     srv.close()
 
 
+def test_requests_with_different_psfs_share_a_launch(ctx):
+    """Stamps of six PSFs fuse into one launch per stamp size (the batch key
+    is the mixture, the size and the flags; each galaxy reads its request's
+    PSF from the server's resident tables).  At 16 x 16 four stamps share a
+    wavefront, so neighbouring lanes read different PSFs.  Each request's
+    stamps equal, bit for bit, those of the same request launched alone
+    (the plain mode) and of a direct render."""
+    import torch
+    from paper_2012_15797_amd.serving import Server
+
+    tr = wl.config4_trace(duration_s=0.01, rate_hz=2000.0, n_psf=6)
+    psfs, mix = _objects(ctx, tr, 6)
+    rng = np.random.Generator(np.random.PCG64(4711))
+    reqs = []
+    for W in (16, 64, 256):
+        for i in range(12 if W < 256 else 6):
+            n = int(rng.integers(1, 40))
+            reqs.append((i % 6, W, wl.draw_galaxies(rng, n, W, (np.arange(n) % 2).astype(np.int32))))
+
+    def submit_all(srv):
+        return [srv.submit(psfs[p], mix, W, g.x, g.y, g.flux, g.r_e, g.e1, g.e2, mix_id=g.mix_id)
+                for p, W, g in reqs]
+
+    srv = Server(ctx, mem_budget_bytes=8 << 30, n_streams=1, max_batch_stamps=1 << 16)
+    # first pass: the server enters each PSF at each size (its transform is made
+    # then, on this thread)
+    for t in submit_all(srv):
+        srv.wait(t)
+        srv.release(t)
+    l1 = srv.stats()["launches"]
+    # a long request holds the only stream while the others queue behind it
+    blk = wl.draw_galaxies(rng, 20000, 256, 0)
+    tb = srv.submit(psfs[0], mix, 256, blk.x, blk.y, blk.flux, blk.r_e, blk.e1, blk.e2)
+    tickets = submit_all(srv)
+    srv.wait(tb)
+    srv.release(tb)
+    fused = []
+    for t in tickets:
+        srv.wait(t)
+        fused.append(srv.result(t).clone())
+        srv.release(t)
+    st = srv.stats()
+    srv.close()
+    assert st["done"] == 2 * len(reqs) + 1
+    assert st["launches"] - l1 <= 1 + 3 + 1, (st, l1)   # a launch per PSF would take 1 + 6 + 6 + 6
+    plain = Server(ctx, mem_budget_bytes=8 << 30, n_streams=1, max_batch_stamps=0)
+    for t, (p, W, g), got in zip(submit_all(plain), reqs, fused):
+        plain.wait(t)
+        alone = plain.result(t)
+        torch.cuda.synchronize()
+        assert torch.equal(got, alone)
+        assert torch.equal(got, _direct(ctx, psfs[p], mix, dict(gal=g, W=W)))
+        plain.release(t)
+    assert plain.stats()["launches"] == len(reqs)
+    plain.close()
+
+
 def test_backpressure_small_budget(ctx):
     import torch
     from paper_2012_15797_amd.serving import Server
@@ -65,7 +122,7 @@ def test_backpressure_small_budget(ctx):
     tr = wl.config4_trace(duration_s=0.02, rate_hz=2000.0, restricted=True)
     reqs = tr["requests"][:12]
     psfs, mix = _objects(ctx, tr, 1)
-    biggest = max(len(r["gal"]) for r in reqs) * (64 * 64 * 4 + 28)
+    biggest = (max(len(r["gal"]) for r in reqs) * (64 * 64 * 4 + 32) + 255) // 256 * 256
     srv = Server(ctx, mem_budget_bytes=biggest + 1, n_streams=2, max_batch_stamps=1 << 16)
     tickets = [srv.submit(psfs[0], mix, 64, r["gal"].x, r["gal"].y, r["gal"].flux, r["gal"].r_e,
                           r["gal"].e1, r["gal"].e2) for r in reqs]
@@ -93,14 +150,20 @@ def test_rejects_request_larger_than_budget(ctx):
 def test_plain_mode_and_trace_replay(ctx):
     from paper_2012_15797_amd.serving import Server, replay_trace
 
+    import torch
+
     tr = wl.config4_trace(duration_s=0.25, rate_hz=2000.0, restricted=True)
     psfs, mix = _objects(ctx, tr, 1)
+    picked = [0, len(tr["requests"]) // 2, len(tr["requests"]) - 1]
     for max_batch, n_streams in ((0, 1), (1 << 16, 2)):
         srv = Server(ctx, mem_budget_bytes=8 << 30, n_streams=n_streams, max_batch_stamps=max_batch)
-        res = replay_trace(srv, tr["requests"], psfs, mix)
+        keep = {i: torch.full((len(tr["requests"][i]["gal"]), 64, 64), float("nan"), device="cuda") for i in picked}
+        res = replay_trace(srv, tr["requests"], psfs, mix, keep=keep)
         assert res["requests"] == len(tr["requests"]) and res["p99_ms"] > 0
         if max_batch == 0:
             assert res["launches"] == res["requests"]
+        for i in picked:  # the kept stamps are the requests' own
+            assert torch.equal(keep[i], _direct(ctx, psfs[0], mix, tr["requests"][i]))
         srv.close()
 
 
@@ -128,7 +191,7 @@ def test_native_replay_errors(ctx):
         reqs = (gfc_request * len(items))(*[p[0] for p in items])
         t = np.ascontiguousarray(times, np.float64)
         lag = np.zeros(len(items))
-        call("gfc_server_replay", srv.handle, reqs, t.ctypes.data_as(D_p), len(items), lag.ctypes.data_as(D_p), None)
+        call("gfc_server_replay", srv.handle, reqs, t.ctypes.data_as(D_p), len(items), None, lag.ctypes.data_as(D_p), None)
         return lag
 
     with pytest.raises(gfc.GfcError) as e:
