@@ -136,9 +136,11 @@ BWD_NOISE_SEED = wl.SEED_BASE + 55    # upstream gradient of the adjoint line: u
 
 def serving_traces(seconds):
     """(label, rate, seconds, restricted) of the replayed traces: the full
-    serving configuration (64 PSFs, stamps 16..256) and the 64x64 one-PSF
-    variant at the nominal and a saturating rate."""
-    return (("", 2000.0, seconds, False), ("restricted64_", 2000.0, min(seconds, 3.0), True),
+    serving configuration (64 PSFs, stamps 16..256) at its nominal rate and
+    at ten times that, and the 64x64 one-PSF variant at the nominal and the
+    tenfold rate."""
+    return (("", 2000.0, seconds, False), ("saturated_", 20000.0, min(seconds, 2.0), False),
+            ("restricted64_", 2000.0, min(seconds, 3.0), True),
             ("saturated64_", 20000.0, min(seconds, 1.0), True))
 
 
