@@ -180,6 +180,11 @@ typedef struct {
   const float* psf_x;    /* device, image position (X, Y) of each galaxy at which */
   const float* psf_y;    /* a spatially varying PSF is evaluated; required by an
                             eigen-PSF, ignored (may be NULL) for a constant PSF */
+  const float* mix_amp;  /* device, [n_tables][GFC_KMAX] float32 amplitudes used by
+                            this call instead of the mixture's (its component counts
+                            and variances still apply), or NULL; the mixture itself
+                            is not changed.  Not used by the Sersic and composite
+                            renders, which build their own tables. */
 } gfc_galaxies;
 
 /* Steps 3-8 for n galaxies into stamps of size W, asynchronously on

@@ -40,7 +40,7 @@ class gfc_galaxies(ctypes.Structure):
         ("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("flux", ctypes.c_void_p),
         ("r_e", ctypes.c_void_p), ("e1", ctypes.c_void_p), ("e2", ctypes.c_void_p),
         ("mix_id", ctypes.c_void_p), ("cd", ctypes.POINTER(ctypes.c_float)),
-        ("psf_x", ctypes.c_void_p), ("psf_y", ctypes.c_void_p),
+        ("psf_x", ctypes.c_void_p), ("psf_y", ctypes.c_void_p), ("mix_amp", ctypes.c_void_p),
     ]
 
 

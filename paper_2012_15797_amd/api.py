@@ -195,7 +195,7 @@ class SersicFamily:
             self.handle = None
 
 
-def _galaxies(dev, x, y, flux, r_e, e1, e2, mix_id, cd, psf_x=None, psf_y=None):
+def _galaxies(dev, x, y, flux, r_e, e1, e2, mix_id, cd, psf_x=None, psf_y=None, mix_amp=None, n_tables=0):
     ts = [_f32_dev(t, dev, nm) for t, nm in
           zip((x, y, flux, r_e, e1, e2), ("x", "y", "flux", "r_e", "e1", "e2"))]
     n = ts[0].numel()
@@ -222,17 +222,24 @@ def _galaxies(dev, x, y, flux, r_e, e1, e2, mix_id, cd, psf_x=None, psf_y=None):
         if pos[0].numel() != n or pos[1].numel() != n:
             raise ValueError("psf_x/psf_y length differs")
         g.psf_x, g.psf_y = pos[0].data_ptr(), pos[1].data_ptr()
-    keep = (ts, mid, cdbuf, pos)
+    amp = None
+    if mix_amp is not None:
+        amp = _f32_dev(mix_amp, dev, "mix_amp")
+        if amp.numel() != n_tables * GFC_KMAX:
+            raise ValueError("mix_amp must hold n_tables x 16 values")
+        g.mix_amp = amp.data_ptr()
+    keep = (ts, mid, cdbuf, pos, amp)
     return g, n, keep
 
 
 def gfc_render_stamps(ctx, psf, mix, x, y, flux, r_e, e1, e2, W, mix_id=None, flags=0, cd=None,
-                      out=None, psf_x=None, psf_y=None):
+                      out=None, psf_x=None, psf_y=None, mix_amp=None):
     """Forward render (gfc_render_stamps): float32 stamps [n, W, W] on the
     context's device, enqueued on torch's current stream.  psf_x/psf_y: the
-    galaxies' image positions, for a spatially varying PSF."""
+    galaxies' image positions, for a spatially varying PSF.  mix_amp: an
+    [n_tables, 16] amplitude table for this call (the mixture is unchanged)."""
     dev = ctx.torch_device
-    g, n, keep = _galaxies(dev, x, y, flux, r_e, e1, e2, mix_id, cd, psf_x, psf_y)
+    g, n, keep = _galaxies(dev, x, y, flux, r_e, e1, e2, mix_id, cd, psf_x, psf_y, mix_amp, mix.n_tables)
     if out is None:
         out = torch.empty((n, W, W), dtype=torch.float32, device=dev)
     elif out.dtype != torch.float32 or not out.is_contiguous() or out.numel() != n * W * W:
@@ -291,11 +298,12 @@ def gfc_backward_workspace_bytes(n: int) -> int:
 
 
 def gfc_render_stamps_backward(ctx, psf, mix, x, y, flux, r_e, e1, e2, W, grad_out, mix_id=None,
-                               flags=0, cd=None, grad_params=None, grad_amp=None, workspace=None):
+                               flags=0, cd=None, grad_params=None, grad_amp=None, workspace=None, mix_amp=None):
     """Adjoint (gfc_render_stamps_backward): returns (grad_params [n, 6] =
-    dL/d(x, y, flux, log r_e, e1, e2), grad_amp [n_tables, 16] accumulated)."""
+    dL/d(x, y, flux, log r_e, e1, e2), grad_amp [n_tables, 16] accumulated).
+    mix_amp: the per-call amplitude table of the forward render, if it had one."""
     dev = ctx.torch_device
-    g, n, keep = _galaxies(dev, x, y, flux, r_e, e1, e2, mix_id, cd)
+    g, n, keep = _galaxies(dev, x, y, flux, r_e, e1, e2, mix_id, cd, mix_amp=mix_amp, n_tables=mix.n_tables)
     go = grad_out.to(dev, torch.float32).contiguous()
     if go.numel() != n * W * W:
         raise ValueError("grad_out must hold n*W*W elements")

@@ -8,29 +8,26 @@ e2 and, when `amp` is given, the mixture amplitudes [n_tables, 16].
 
 from __future__ import annotations
 
-import ctypes
-
 import torch
 
 from . import api
-from ._lib import GFC_KMAX, call
+from ._lib import GFC_KMAX
 
 
 class RenderStamps(torch.autograd.Function):
     @staticmethod
     def forward(ctx, psf, mix, W, flags, cd, mix_id, x, y, flux, r_e, e1, e2, amp):
         gctx = psf.ctx
-        if amp is not None:
+        a = None
+        if amp is not None:  # a per-call table: the mixture's own amplitudes stay as they are
             a = amp.detach().to(gctx.torch_device, torch.float32).contiguous()
             if a.numel() != mix.n_tables * GFC_KMAX:
                 raise ValueError("amp must hold n_tables x 16 values")
-            call("gfc_mix_set_amp", mix.handle, ctypes.c_void_p(a.data_ptr()),
-                 api._stream_ptr(gctx.device))
-            ctx.amp_keep = a
         out = api.gfc_render_stamps(gctx, psf, mix, x, y, flux, r_e, e1, e2, W, mix_id=mix_id,
-                                    flags=flags, cd=cd)
+                                    flags=flags, cd=cd, mix_amp=a)
         ctx.psf, ctx.mix, ctx.W, ctx.flags, ctx.cd, ctx.mix_id = psf, mix, W, flags, cd, mix_id
         ctx.has_amp = amp is not None
+        ctx.amp_keep = a
         ctx.save_for_backward(x, y, flux, r_e, e1, e2)
         return out
 
@@ -38,12 +35,9 @@ class RenderStamps(torch.autograd.Function):
     def backward(ctx, grad_out):
         x, y, flux, r_e, e1, e2 = ctx.saved_tensors
         gctx = ctx.psf.ctx
-        if ctx.has_amp:  # the forward may have been followed by other amplitude updates
-            call("gfc_mix_set_amp", ctx.mix.handle, ctypes.c_void_p(ctx.amp_keep.data_ptr()),
-                 api._stream_ptr(gctx.device))
         gp, ga = api.gfc_render_stamps_backward(
             gctx, ctx.psf, ctx.mix, x, y, flux, r_e, e1, e2, ctx.W, grad_out.contiguous(),
-            mix_id=ctx.mix_id, flags=ctx.flags, cd=ctx.cd)
+            mix_id=ctx.mix_id, flags=ctx.flags, cd=ctx.cd, mix_amp=ctx.amp_keep)
         r = r_e.to(gp.device, torch.float32)
         grads = [gp[:, 0], gp[:, 1], gp[:, 2], gp[:, 3] / r, gp[:, 4], gp[:, 5]]
         grads = [g.to(t.device, t.dtype).reshape(t.shape) if t.requires_grad else None
@@ -55,5 +49,7 @@ class RenderStamps(torch.autograd.Function):
 def render(psf, mix, x, y, flux, r_e, e1, e2, W, amp=None, mix_id=None, flags=0, cd=None):
     """Differentiable render.  Galaxy parameters are float32 device tensors
     of length n; amp (optional) is a float32 [n_tables, 16] tensor of mixture
-    amplitudes that replaces the table's amplitudes for this call."""
+    amplitudes used by this call (and its backward) instead of the table's;
+    the mixture itself is not changed, so it may be shared with a server or
+    other renders."""
     return RenderStamps.apply(psf, mix, int(W), int(flags), cd, mix_id, x, y, flux, r_e, e1, e2, amp)

@@ -28,7 +28,9 @@ MB_SOURCES = ["microbench.hip"]
 ARCH = "gfx950"
 
 SOURCES = [
+    "gfc_error.cpp",
     "gfc_host.cpp",
+    "sched.cpp",
     "render_dispatch.cpp",
     "render_fwd.hip",
     "render_large.hip",

@@ -17,16 +17,7 @@
 
 using gfc::RenderArgs;
 
-namespace {
-thread_local std::string g_last_error;
-}
-
 namespace gfc {
-
-gfc_status fail(gfc_status s, const std::string& msg) {
-  g_last_error = msg;
-  return s;
-}
 
 gfc_status hip_fail(hipError_t e, const char* what) {
   return fail(GFC_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
@@ -113,7 +104,7 @@ gfc_status fill_render_args(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix* mix, cons
   a->e1 = gal->e1;
   a->e2 = gal->e2;
   a->mix_id = gal->mix_id;
-  a->amp = mix->d_amp;
+  a->amp = gal->mix_amp ? gal->mix_amp : mix->d_amp;  // a per-call amplitude table leaves the mixture as it is
   a->var = mix->d_var;
   a->K = mix->d_K;
   a->n_tables = mix->n_tables;
@@ -163,22 +154,6 @@ void attach_spectrum(RenderArgs* a, const PsfSpectrum* spec) {
 using namespace gfc;
 
 extern "C" {
-
-const char* gfc_status_str(gfc_status s) {
-  switch (s) {
-    case GFC_OK: return "ok";
-    case GFC_EINVAL: return "invalid argument";
-    case GFC_EUNSUPPORTED: return "unsupported";
-    case GFC_ENOMEM: return "out of memory";
-    case GFC_EDEVICE: return "device error";
-    case GFC_EBUSY: return "busy";
-    case GFC_EREJECTED: return "rejected";
-    case GFC_ETIMEOUT: return "timed out";
-  }
-  return "unknown status";
-}
-
-const char* gfc_last_error(void) { return g_last_error.c_str(); }
 
 int gfc_stamp_size_supported(int W) { return stamp_size_ok(W) ? 1 : 0; }
 

@@ -11,6 +11,7 @@
 
 #include "gfc.h"
 #include "gfc_device.hpp"
+#include "gfc_error.hpp"
 
 struct gfc_ctx {
   int device = 0;
@@ -56,8 +57,7 @@ struct gfc_mix {
 
 namespace gfc {
 
-gfc_status fail(gfc_status s, const std::string& msg);
-gfc_status hip_fail(hipError_t e, const char* what);
+gfc_status hip_fail(hipError_t e, const char* what);  // fail() with the HIP error's text
 bool stamp_size_ok(int W);
 
 class DeviceGuard {

@@ -1,25 +1,14 @@
-// Serving: continuous batching of render requests (gfc_server_*), and the same
-// scheduling core driven through caller callbacks (gfc_sched_*).
+// Serving (gfc_server_*): continuous batching of render requests on the
+// device.  The policy is the scheduling core of sched_core.hpp, run by its
+// threaded loop; this file supplies the HIP executor (pinned staging, one
+// launch per batch on the batch's stream, completion events, batch memory
+// from an arena reserved at creation) and the server's PSF tables.
 //
-// Policy, identical for both front ends:
-//   admission  strict FIFO: the oldest pending request is admitted when its
-//              bytes fit in what the budget has left; nothing behind it
-//              overtakes it (no starvation of large requests).
-//   batching   among admitted requests, the oldest one picks the key
-//              (mixture, stamp size, flags), compared as that whole tuple;
-//              later admitted requests with the same key join in arrival
-//              order up to max_batch_stamps, whatever their PSFs: each galaxy
-//              of a batch carries the index of its request's PSF into the
-//              server's device tables of resident PSF spectra and Gaussians.
-//              max_batch_stamps <= 0 launches every request alone (plain).
-//   PSFs       the first request naming a PSF at a stamp size enters the
-//              PSF's cached spectrum for that size (filled then if needed)
-//              and its Gaussian in those tables, on the submitting thread:
-//              the launch thread never fills a cache.
-//   streams    at most one batch in flight per stream; requests arriving
-//              while every stream is busy are admitted and wait for the next
-//              free stream, where they are fused with whatever else arrived.
-//   memory     a request is charged its bytes from admission to release.
+// PSFs: the first request naming a PSF at a stamp size enters the PSF's
+// cached spectrum for that size (filled then if needed) and its Gaussian in
+// the server's device tables, on the submitting thread; each galaxy of a
+// batch carries the index of its request's PSF, so requests with different
+// PSFs share a launch and the launch thread never fills a cache.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,7 +17,6 @@
 #include <cmath>
 #include <condition_variable>
 #include <cstring>
-#include <deque>
 #include <iterator>
 #include <map>
 #include <memory>
@@ -39,251 +27,23 @@
 
 #include "gfc_internal.hpp"
 #include "gfc_launch.hpp"
+#include "sched_core.hpp"
 
 namespace gfc {
 namespace serve {
 
-// Batching key, compared as a whole: (mixture, stamp size << 32 | flags) for
-// the server; (caller's key, 0) for the callback scheduler.
-struct BatchKey {
-  uint64_t a = 0, b = 0;
-  bool operator==(const BatchKey& o) const { return a == o.a && b == o.b; }
-};
-
-struct Req {
-  uint64_t ticket = 0;
-  BatchKey key;
-  int64_t n = 0;
-  size_t bytes = 0;
-  int state = GFC_REQ_PENDING;
-  gfc_status status = GFC_OK;
-  bool charged = false;
-  double t_submit = 0.0, t_done = 0.0;
-  uint64_t batch = 0;
-  int64_t offset = 0;  // first stamp of this request within its batch
-  const float* out_ptr = nullptr;  // device stamps once launched
-  // payload used by the device executor
-  gfc_psf* psf = nullptr;
-  int psf_slot = 0;               // index of the PSF in the server's device tables
-  const gfc_mix* mix = nullptr;
-  int W = 0;
-  unsigned flags = 0;
-  std::vector<float> params;      // SoA [6][n]
-  std::vector<int32_t> mix_id;    // [n] or empty
-};
-
-struct Batch {
-  uint64_t id = 0;
-  BatchKey key;
-  int stream = -1;
-  std::vector<Req*> reqs;
-  int64_t n = 0;
-  bool finished = false;
-  int live = 0;  // requests not yet released
-  // device executor state
+// Per-batch state of the HIP executor.
+struct HipBatch : BatchState {
   void* mem = nullptr;
   hipEvent_t event = nullptr;
-  std::vector<hipEvent_t> reads;  // copies out of `mem` on callers' streams (gfc_server_copy)
-  size_t arena_off = 0, arena_size = 0;  // `mem` is arena_size bytes of the server's arena (0: its own allocation)
+  std::vector<hipEvent_t> reads;         // copies out of `mem` on callers' streams (gfc_server_copy)
+  size_t arena_off = 0, arena_size = 0;  // `mem` is arena_size bytes of the arena (0: its own allocation)
 };
 
-class Executor {
- public:
-  virtual ~Executor() = default;
-  virtual double now() = 0;
-  virtual int launch(Batch& b) = 0;     // 0 = ok
-  virtual int poll(Batch& b) = 0;       // 1 done, 0 running, <0 failed
-  virtual void release(Batch& b) = 0;   // after completion and after every request is released
-};
-
-class Core {
- public:
-  Core(Executor* ex, size_t budget, int n_streams, int64_t max_batch)
-      : ex_(ex), budget_(budget), max_batch_(max_batch), slots_(std::max(1, n_streams), 0) {
-    t0_ = ex_->now();
-  }
-
-  gfc_status submit(std::unique_ptr<Req> r, uint64_t* ticket) {
-    if (r->bytes > budget_) return fail(GFC_EREJECTED, "request exceeds the memory budget");
-    r->ticket = next_ticket_++;
-    r->t_submit = ex_->now();
-    r->state = GFC_REQ_PENDING;
-    pending_.push_back(r.get());
-    *ticket = r->ticket;
-    reqs_[r->ticket] = std::move(r);
-    return GFC_OK;
-  }
-
-  // One pass: reap finished batches, admit, launch.  Returns true if any
-  // request changed state.
-  bool step() {
-    bool changed = false;
-    for (size_t s = 0; s < slots_.size(); ++s) {
-      if (!slots_[s]) continue;
-      Batch& b = *batches_[slots_[s]];
-      const int st = ex_->poll(b);
-      if (st == 0) continue;
-      const double t = ex_->now();
-      for (Req* r : b.reqs) {
-        r->t_done = t;
-        if (st > 0) {
-          r->state = GFC_REQ_DONE;
-          latencies_ms_.push_back((t - r->t_submit) * 1e3);
-          stamps_done_ += r->n;
-          t_last_ = t;
-        } else {
-          r->state = GFC_REQ_FAILED;
-          r->status = GFC_EDEVICE;
-        }
-      }
-      b.finished = true;
-      slots_[s] = 0;
-      changed = true;
-      maybe_free(b);
-    }
-    while (!pending_.empty()) {
-      Req* r = pending_.front();
-      if (used_ + r->bytes > budget_) break;
-      used_ += r->bytes;
-      r->charged = true;
-      r->state = GFC_REQ_ADMITTED;
-      admitted_.push_back(r);
-      pending_.pop_front();
-      changed = true;
-    }
-    for (size_t s = 0; s < slots_.size() && !admitted_.empty(); ++s) {
-      if (slots_[s]) continue;
-      auto b = std::make_unique<Batch>();
-      b->id = next_batch_++;
-      b->stream = (int)s;
-      b->key = admitted_.front()->key;
-      for (auto it = admitted_.begin(); it != admitted_.end();) {
-        Req* r = *it;
-        const bool first = b->reqs.empty();
-        if (!(r->key == b->key)) { ++it; continue; }
-        if (!first && (max_batch_ <= 0 || b->n + r->n > max_batch_)) break;
-        r->offset = b->n;
-        r->batch = b->id;
-        r->state = GFC_REQ_LAUNCHED;
-        b->n += r->n;
-        b->reqs.push_back(r);
-        it = admitted_.erase(it);
-        if (max_batch_ <= 0) break;
-      }
-      b->live = (int)b->reqs.size();
-      Batch& ref = *b;
-      batches_[b->id] = std::move(b);
-      ++launches_;
-      if (ex_->launch(ref) != 0) {
-        for (Req* r : ref.reqs) {
-          r->state = GFC_REQ_FAILED;
-          if (r->status == GFC_OK) r->status = GFC_EDEVICE;
-          r->t_done = ex_->now();
-        }
-        ref.finished = true;
-        maybe_free(ref);
-      } else {
-        slots_[s] = ref.id;
-      }
-      changed = true;
-    }
-    return changed;
-  }
-
-  Req* find(uint64_t t) {
-    auto it = reqs_.find(t);
-    return it == reqs_.end() ? nullptr : it->second.get();
-  }
-  Batch* batch(uint64_t id) {
-    auto it = batches_.find(id);
-    return it == batches_.end() ? nullptr : it->second.get();
-  }
-
-  gfc_status release(uint64_t t) {
-    Req* r = find(t);
-    if (!r) return fail(GFC_EINVAL, "unknown ticket");
-    if (r->state != GFC_REQ_DONE && r->state != GFC_REQ_FAILED) return fail(GFC_EBUSY, "request still in flight");
-    if (r->charged) used_ -= r->bytes;
-    if (r->batch) {
-      auto it = batches_.find(r->batch);
-      if (it != batches_.end()) {
-        it->second->live--;
-        maybe_free(*it->second);
-      }
-    }
-    reqs_.erase(t);
-    return GFC_OK;
-  }
-
-  bool busy() const {
-    if (!pending_.empty() || !admitted_.empty()) return true;
-    for (uint64_t s : slots_)
-      if (s) return true;
-    return false;
-  }
-  bool any_in_flight() const {
-    for (uint64_t s : slots_)
-      if (s) return true;
-    return false;
-  }
-
-  void stats(double* p50, double* p99, double* mx, double* sps, uint64_t* nl, uint64_t* nd) const {
-    std::vector<double> v = latencies_ms_;
-    std::sort(v.begin(), v.end());
-    auto q = [&](double f) {  // nearest rank
-      if (v.empty()) return 0.0;
-      const double rank = std::ceil(f * (double)v.size());
-      const size_t i = rank < 1.0 ? 0 : std::min(v.size() - 1, (size_t)rank - 1);
-      return v[i];
-    };
-    if (p50) *p50 = q(0.5);
-    if (p99) *p99 = q(0.99);
-    if (mx) *mx = v.empty() ? 0.0 : v.back();
-    if (sps) *sps = (t_last_ > t0_) ? (double)stamps_done_ / (t_last_ - t0_) : 0.0;
-    if (nl) *nl = launches_;
-    if (nd) *nd = v.size();
-  }
-
-  // Fails every request that has not been admitted yet (server shutdown).
-  void cancel_pending() {
-    const double t = ex_->now();
-    for (Req* r : pending_) {
-      r->state = GFC_REQ_FAILED;
-      r->status = GFC_EBUSY;
-      r->t_done = t;
-    }
-    pending_.clear();
-  }
-
-  size_t used() const { return used_; }
-  uint64_t n_pending() const { return pending_.size(); }
-  // Frees every batch (used by the destructors after draining).
-  void free_all() {
-    for (auto& kv : batches_)
-      if (kv.second->finished) ex_->release(*kv.second);
-    batches_.clear();
-  }
-
- private:
-  void maybe_free(Batch& b) {
-    if (b.finished && b.live <= 0) {
-      ex_->release(b);
-      batches_.erase(b.id);
-    }
-  }
-
-  Executor* ex_;
-  size_t budget_, used_ = 0;
-  int64_t max_batch_;
-  std::vector<uint64_t> slots_;  // batch id in flight per stream (0 = free)
-  std::deque<Req*> pending_, admitted_;
-  std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs_;
-  std::map<uint64_t, std::unique_ptr<Batch>> batches_;
-  uint64_t next_ticket_ = 1, next_batch_ = 1, launches_ = 0;
-  std::vector<double> latencies_ms_;
-  uint64_t stamps_done_ = 0;
-  double t0_ = 0.0, t_last_ = 0.0;
-};
+static HipBatch& hb(Batch& b) {
+  if (!b.state) b.state = std::make_unique<HipBatch>();
+  return static_cast<HipBatch&>(*b.state);
+}
 
 // ---------------------------------------------------------------- device executor
 class HipExecutor : public Executor {
@@ -414,17 +174,18 @@ class HipExecutor : public Executor {
         std::memcpy(hm + r->offset, r->mix_id.data(), r->n * sizeof(int32_t));
       std::fill(hs + r->offset, hs + r->offset + r->n, (int32_t)r->psf_slot);
     }
-    b.arena_size = 0;
-    if (void* m = arena_alloc(out_bytes + par_bytes, &b.arena_off)) {
-      b.mem = m;
-      b.arena_size = align(out_bytes + par_bytes);
-    } else if (hipMallocAsync(&b.mem, out_bytes + par_bytes, s) != hipSuccess) {  // arena full or fragmented
-      b.mem = nullptr;
+    HipBatch& h = hb(b);
+    h.arena_size = 0;
+    if (void* m = arena_alloc(out_bytes + par_bytes, &h.arena_off)) {
+      h.mem = m;
+      h.arena_size = align(out_bytes + par_bytes);
+    } else if (hipMallocAsync(&h.mem, out_bytes + par_bytes, s) != hipSuccess) {  // arena full or fragmented
+      h.mem = nullptr;
       for (Req* r : b.reqs) r->status = GFC_ENOMEM;
       return -1;
     }
-    float* dout = static_cast<float*>(b.mem);
-    float* dpar = reinterpret_cast<float*>(static_cast<char*>(b.mem) + out_bytes);
+    float* dout = static_cast<float*>(h.mem);
+    float* dpar = reinterpret_cast<float*>(static_cast<char*>(h.mem) + out_bytes);
     if (hipMemcpyAsync(dpar, hp, par_bytes, hipMemcpyHostToDevice, s) != hipSuccess) return fail_batch(b);
     gfc_galaxies gal{};
     gal.x = dpar;
@@ -446,40 +207,58 @@ class HipExecutor : public Executor {
     a.n_psf = n_slots_.load();
     a.out = dout;
     if (render_launch(a, W, s) != GFC_OK) return fail_batch(b);
-    b.event = events_[b.stream];
-    if (hipEventRecord(b.event, s) != hipSuccess) return fail_batch(b);
+    h.event = events_[b.stream];
+    if (hipEventRecord(h.event, s) != hipSuccess) return fail_batch(b);
     for (Req* r : b.reqs) r->out_ptr = dout + r->offset * (int64_t)W * W;
     return 0;
   }
   int poll(Batch& b) override {
-    if (!b.event) return -1;
-    const hipError_t e = hipEventQuery(b.event);
+    HipBatch& h = hb(b);
+    if (!h.event) return -1;
+    const hipError_t e = hipEventQuery(h.event);
     if (e == hipSuccess) return 1;
     if (e == hipErrorNotReady) return 0;
     return -1;
   }
-  void release(Batch& b) override {
+  size_t release(Batch& b) override {
     DeviceGuard g(ctx_->device);
-    if (b.arena_size) {
+    HipBatch& h = hb(b);
+    size_t held = 0;
+    if (h.arena_size) {
       // The batch has finished, so only callers' copies can still read the
-      // block: it is free now, or once those copies have completed.
-      if (b.reads.empty()) arena_free(b.arena_off, b.arena_size);
-      else pending_.push_back(Pending{b.arena_off, b.arena_size, std::move(b.reads)});
-      b.reads.clear();
-      b.arena_size = 0;
-      b.mem = nullptr;
+      // block: it is free now, or once those copies have completed (until
+      // then the scheduler keeps it charged to the budget).
+      if (h.reads.empty()) {
+        arena_free(h.arena_off, h.arena_size);
+      } else {
+        pending_.push_back(Pending{h.arena_off, h.arena_size, std::move(h.reads)});
+        held = h.arena_size;
+      }
+      h.reads.clear();
+      h.arena_size = 0;
+      h.mem = nullptr;
     }
     // stream-ordered allocation: reused in this stream's order, so first wait
     // for the copies callers made from it on their own streams
-    for (hipEvent_t ev : b.reads) {
+    for (hipEvent_t ev : h.reads) {
       hipStreamWaitEvent(streams_[b.stream], ev, 0);
       hipEventDestroy(ev);
     }
-    b.reads.clear();
-    if (b.mem) hipFreeAsync(b.mem, streams_[b.stream]);
-    b.mem = nullptr;
-    b.event = nullptr;
+    h.reads.clear();
+    if (h.mem) hipFreeAsync(h.mem, streams_[b.stream]);
+    h.mem = nullptr;
+    h.event = nullptr;
+    return held;
   }
+  size_t reclaimed() override {
+    reclaim();
+    const size_t r = reclaimed_;
+    reclaimed_ = 0;
+    return r;
+  }
+  // Records a caller's copy out of the batch's memory (gfc_server_copy).
+  void add_read(Batch& b, hipEvent_t ev) { hb(b).reads.push_back(ev); }
+
  private:
   int fail_batch(Batch& b) {
     // wait for anything already enqueued on this stream before its memory is reused
@@ -555,6 +334,7 @@ class HipExecutor : public Executor {
       }
       for (hipEvent_t ev : pending_[i].reads) hipEventDestroy(ev);
       arena_free(pending_[i].off, pending_[i].size);
+      reclaimed_ += pending_[i].size;
       pending_[i] = std::move(pending_.back());
       pending_.pop_back();
     }
@@ -563,25 +343,7 @@ class HipExecutor : public Executor {
   size_t arena_bytes_ = 0;
   std::map<size_t, size_t> free_;
   std::vector<Pending> pending_;
-};
-
-// ---------------------------------------------------------------- callback executor
-class CallbackExecutor : public Executor {
- public:
-  explicit CallbackExecutor(const gfc_sched_executor& cb) : cb_(cb) {}
-  double now() override { return cb_.now(cb_.user); }
-  int launch(Batch& b) override {
-    std::vector<uint64_t> t;
-    for (Req* r : b.reqs) t.push_back(r->ticket);
-    return cb_.launch(cb_.user, b.id, b.stream, (int)t.size(), t.data(), b.n);
-  }
-  int poll(Batch& b) override { return cb_.poll(cb_.user, b.id); }
-  void release(Batch& b) override {
-    if (cb_.release) cb_.release(cb_.user, b.id);
-  }
-
- private:
-  gfc_sched_executor cb_;
+  size_t reclaimed_ = 0;  // bytes of pending blocks freed since the scheduler last asked
 };
 
 }  // namespace serve
@@ -593,37 +355,8 @@ using namespace gfc::serve;
 struct gfc_server {
   gfc_ctx* ctx = nullptr;
   std::unique_ptr<HipExecutor> ex;
-  std::unique_ptr<Core> core;
-  std::mutex mu;
-  std::condition_variable cv_work, cv_done;
-  std::thread worker;
-  bool stop = false;
+  std::unique_ptr<Loop> loop;
 };
-
-struct gfc_sched {
-  std::unique_ptr<CallbackExecutor> ex;
-  std::unique_ptr<Core> core;
-};
-
-static void server_loop(gfc_server* s) {
-  std::unique_lock<std::mutex> lock(s->mu);
-  while (true) {
-    if (s->stop) s->core->cancel_pending();  // never admitted: fail rather than wait for budget
-    const bool changed = s->core->step();
-    if (changed || s->stop) s->cv_done.notify_all();
-    if (s->stop && !s->core->busy()) break;
-    if (!s->core->busy()) {
-      s->cv_work.wait(lock, [&] { return s->stop || s->core->busy(); });
-      continue;
-    }
-    if (!changed) {
-      // launches in flight: poll again shortly without holding the lock
-      lock.unlock();
-      std::this_thread::sleep_for(std::chrono::microseconds(20));
-      lock.lock();
-    }
-  }
-}
 
 extern "C" {
 
@@ -636,8 +369,7 @@ gfc_status gfc_server_create(gfc_ctx* ctx, size_t mem_budget_bytes, int n_stream
   if (!s) return fail(GFC_ENOMEM, "server allocation failed");
   s->ctx = ctx;
   s->ex = std::make_unique<HipExecutor>(ctx, n_streams, mem_budget_bytes);
-  s->core = std::make_unique<Core>(s->ex.get(), mem_budget_bytes, n_streams, max_batch_stamps);
-  s->worker = std::thread(server_loop, s);
+  s->loop = std::make_unique<Loop>(s->ex.get(), mem_budget_bytes, n_streams, max_batch_stamps);
   ctx->n_objects++;
   *out = s;
   return GFC_OK;
@@ -673,79 +405,56 @@ gfc_status gfc_server_submit(gfc_server* s, const gfc_request* q, uint64_t* tick
   const float* src[6] = {q->x, q->y, q->flux, q->r_e, q->e1, q->e2};
   for (int f = 0; f < 6; ++f) std::memcpy(r->params.data() + (size_t)f * q->n, src[f], q->n * sizeof(float));
   if (q->mix_id) r->mix_id.assign(q->mix_id, q->mix_id + q->n);
-  std::lock_guard<std::mutex> lock(s->mu);
-  gfc_status st = s->core->submit(std::move(r), ticket);
-  if (st == GFC_OK) s->cv_work.notify_one();
-  return st;
+  return s->loop->submit(std::move(r), ticket);
 }
 
 gfc_status gfc_server_poll(gfc_server* s, uint64_t ticket, int* done, const float** out_dev,
                            gfc_status* status_out) {
   if (!s) return fail(GFC_EINVAL, "null server");
-  std::lock_guard<std::mutex> lock(s->mu);
-  Req* r = s->core->find(ticket);
-  if (!r) return fail(GFC_EINVAL, "unknown ticket");
-  const bool fin = r->state == GFC_REQ_DONE || r->state == GFC_REQ_FAILED;
-  if (done) *done = fin ? 1 : 0;
-  if (status_out) *status_out = r->status;
-  if (out_dev) *out_dev = (r->state == GFC_REQ_DONE) ? r->out_ptr : nullptr;
-  return GFC_OK;
+  return s->loop->poll(ticket, done, out_dev, status_out);
 }
 
 gfc_status gfc_server_wait(gfc_server* s, uint64_t ticket, int timeout_ms, const float** out_dev) {
   if (!s) return fail(GFC_EINVAL, "null server");
-  std::unique_lock<std::mutex> lock(s->mu);
-  Req* r = s->core->find(ticket);
-  if (!r) return fail(GFC_EINVAL, "unknown ticket");
-  auto fin = [&] { return r->state == GFC_REQ_DONE || r->state == GFC_REQ_FAILED; };
-  if (timeout_ms < 0) {
-    s->cv_done.wait(lock, fin);
-  } else if (!s->cv_done.wait_for(lock, std::chrono::milliseconds(timeout_ms), fin)) {
-    return fail(GFC_ETIMEOUT, "request not finished within the timeout");
-  }
-  if (out_dev) *out_dev = (r->state == GFC_REQ_DONE) ? r->out_ptr : nullptr;
-  if (r->state == GFC_REQ_FAILED) return fail(r->status, "request failed");
-  return GFC_OK;
+  return s->loop->wait(ticket, timeout_ms, out_dev);
 }
 
 gfc_status gfc_server_copy(gfc_server* s, uint64_t ticket, float* dst, void* hip_stream) {
   if (!s || !dst) return fail(GFC_EINVAL, "null argument");
-  std::lock_guard<std::mutex> lock(s->mu);
-  Req* r = s->core->find(ticket);
-  if (!r) return fail(GFC_EINVAL, "unknown ticket");
-  if (r->state != GFC_REQ_DONE) return fail(r->state == GFC_REQ_FAILED ? r->status : GFC_EBUSY, "request not done");
-  DeviceGuard g(s->ctx->device);
-  hipError_t e = hipMemcpyAsync(dst, r->out_ptr, (size_t)r->n * r->W * r->W * sizeof(float),
-                                hipMemcpyDeviceToDevice, (hipStream_t)hip_stream);
-  if (e != hipSuccess) return hip_fail(e, "copy of request stamps");
-  // the batch's memory is freed only after this copy (see HipExecutor::release)
-  hipEvent_t ev = nullptr;
-  e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventRecord(ev, (hipStream_t)hip_stream);
-  if (e != hipSuccess) {
-    if (ev) hipEventDestroy(ev);
-    hipStreamSynchronize((hipStream_t)hip_stream);  // no event: finish the copy here instead
+  return s->loop->locked([&](Core& core) -> gfc_status {
+    Req* r = core.find(ticket);
+    if (!r) return fail(GFC_EINVAL, "unknown ticket");
+    if (r->state != GFC_REQ_DONE)
+      return fail(r->state == GFC_REQ_FAILED ? r->status : GFC_EBUSY, "request not done");
+    DeviceGuard g(s->ctx->device);
+    hipError_t e = hipMemcpyAsync(dst, r->out_ptr, (size_t)r->n * r->W * r->W * sizeof(float),
+                                  hipMemcpyDeviceToDevice, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return hip_fail(e, "copy of request stamps");
+    // the batch's memory is reused only after this copy (see HipExecutor::release)
+    hipEvent_t ev = nullptr;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev, (hipStream_t)hip_stream);
+    if (e != hipSuccess) {
+      if (ev) hipEventDestroy(ev);
+      hipStreamSynchronize((hipStream_t)hip_stream);  // no event: finish the copy here instead
+      return GFC_OK;
+    }
+    Batch* b = core.batch(r->batch);
+    if (b) s->ex->add_read(*b, ev);
+    else hipEventDestroy(ev);
     return GFC_OK;
-  }
-  Batch* b = s->core->batch(r->batch);
-  if (b) b->reads.push_back(ev);
-  else hipEventDestroy(ev);
-  return GFC_OK;
+  });
 }
 
 gfc_status gfc_server_release(gfc_server* s, uint64_t ticket) {
   if (!s) return fail(GFC_EINVAL, "null server");
-  std::lock_guard<std::mutex> lock(s->mu);
-  gfc_status st = s->core->release(ticket);
-  if (st == GFC_OK) s->cv_work.notify_one();  // budget freed: admission may proceed
-  return st;
+  return s->loop->release(ticket);
 }
 
 gfc_status gfc_server_stats(gfc_server* s, double* p50_ms, double* p99_ms, double* max_ms, double* stamps_per_s,
                             uint64_t* n_launches, uint64_t* n_done) {
   if (!s) return fail(GFC_EINVAL, "null server");
-  std::lock_guard<std::mutex> lock(s->mu);
-  s->core->stats(p50_ms, p99_ms, max_ms, stamps_per_s, n_launches, n_done);
+  s->loop->stats(p50_ms, p99_ms, max_ms, stamps_per_s, n_launches, n_done);
   return GFC_OK;
 }
 
@@ -831,82 +540,12 @@ gfc_status gfc_server_replay(gfc_server* s, const gfc_request* reqs, const doubl
 
 gfc_status gfc_server_destroy(gfc_server* s) {
   if (!s) return fail(GFC_EINVAL, "null server");
-  {
-    std::lock_guard<std::mutex> lock(s->mu);
-    s->stop = true;
-  }
-  s->cv_work.notify_all();
-  s->worker.join();
-  s->core->free_all();
-  s->core.reset();
+  s->loop->shutdown();  // drains, joins the loop's thread, frees the batches
+  s->loop.reset();
   s->ex.reset();
   s->ctx->n_objects--;
   delete s;
   return GFC_OK;
 }
 
-// ---------------------------------------------------------------- callback front end
-gfc_status gfc_sched_create(const gfc_sched_executor* ex, size_t mem_budget_bytes, int n_streams,
-                            int64_t max_batch_stamps, gfc_sched** out) {
-  if (!ex || !out || !ex->now || !ex->launch || !ex->poll) return fail(GFC_EINVAL, "null argument");
-  if (n_streams < 1 || n_streams > 64) return fail(GFC_EINVAL, "n_streams must be 1..64");
-  auto* s = new (std::nothrow) gfc_sched();
-  if (!s) return fail(GFC_ENOMEM, "allocation failed");
-  s->ex = std::make_unique<CallbackExecutor>(*ex);
-  s->core = std::make_unique<Core>(s->ex.get(), mem_budget_bytes, n_streams, max_batch_stamps);
-  *out = s;
-  return GFC_OK;
-}
-
-gfc_status gfc_sched_submit(gfc_sched* s, uint64_t key, int64_t n_stamps, size_t bytes, uint64_t* ticket) {
-  if (!s || !ticket || n_stamps < 1) return fail(GFC_EINVAL, "bad argument");
-  auto r = std::make_unique<Req>();
-  r->key.a = key;
-  r->n = n_stamps;
-  r->bytes = bytes;
-  return s->core->submit(std::move(r), ticket);
-}
-
-gfc_status gfc_sched_step(gfc_sched* s) {
-  if (!s) return fail(GFC_EINVAL, "null scheduler");
-  s->core->step();
-  return GFC_OK;
-}
-
-gfc_status gfc_sched_query(gfc_sched* s, uint64_t ticket, int* state, uint64_t* batch) {
-  if (!s) return fail(GFC_EINVAL, "null scheduler");
-  Req* r = s->core->find(ticket);
-  if (!r) return fail(GFC_EINVAL, "unknown ticket");
-  if (state) *state = r->state;
-  if (batch) *batch = r->batch;
-  return GFC_OK;
-}
-
-gfc_status gfc_sched_release(gfc_sched* s, uint64_t ticket) {
-  if (!s) return fail(GFC_EINVAL, "null scheduler");
-  return s->core->release(ticket);
-}
-
-gfc_status gfc_sched_usage(gfc_sched* s, size_t* bytes_in_use, uint64_t* n_pending) {
-  if (!s) return fail(GFC_EINVAL, "null scheduler");
-  if (bytes_in_use) *bytes_in_use = s->core->used();
-  if (n_pending) *n_pending = s->core->n_pending();
-  return GFC_OK;
-}
-
-gfc_status gfc_sched_stats(gfc_sched* s, double* p50_ms, double* p99_ms, double* max_ms, double* stamps_per_s,
-                           uint64_t* n_launches, uint64_t* n_done) {
-  if (!s) return fail(GFC_EINVAL, "null scheduler");
-  s->core->stats(p50_ms, p99_ms, max_ms, stamps_per_s, n_launches, n_done);
-  return GFC_OK;
-}
-
-gfc_status gfc_sched_destroy(gfc_sched* s) {
-  if (!s) return fail(GFC_EINVAL, "null scheduler");
-  s->core->free_all();
-  delete s;
-  return GFC_OK;
-}
-
 }  // extern "C"
-

@@ -165,13 +165,27 @@ def test_autograd_function_matches_adjoint(ctx):
     dev = torch.device("cuda")
     t = lambda a: torch.tensor(a, device=dev, requires_grad=True)
     x, y, fl, re, e1, e2 = map(t, (gal.x, gal.y, gal.flux, gal.r_e, gal.e1, gal.e2))
-    amp = torch.tensor(cfg["mix"].as_f32().amp.astype(np.float32), device=dev, requires_grad=True)
+    m = cfg["mix"].as_f32()
+    table = np.asarray(m.amp, np.float32)
+    new_amp = (table * np.linspace(0.5, 1.5, 16, dtype=np.float32)[None, :]).astype(np.float32)
+    amp = torch.tensor(new_amp, device=dev, requires_grad=True)
     g = torch.as_tensor(rng.standard_normal((n, W, W)).astype(np.float32), device=dev)
+    before = gfc.gfc_render_stamps(ctx, psf, mix, gal.x, gal.y, gal.flux, gal.r_e, gal.e1, gal.e2, W)
     out = gfc.render(psf, mix, x, y, fl, re, e1, e2, W, amp=amp)
     (out * g).sum().backward()
     gp, ga = gfc.gfc_render_stamps_backward(ctx, psf, mix, gal.x, gal.y, gal.flux, gal.r_e, gal.e1,
-                                            gal.e2, W, g)
+                                            gal.e2, W, g, mix_amp=amp.detach())
     torch.cuda.synchronize()
+    # the per-call amplitudes leave the shared mixture as it was ...
+    after = gfc.gfc_render_stamps(ctx, psf, mix, gal.x, gal.y, gal.flux, gal.r_e, gal.e1, gal.e2, W)
+    torch.cuda.synchronize()
+    assert torch.equal(before, after) and not torch.equal(before, out.detach())
+    # ... and render as a mixture made with them would
+    mix2 = gfc.Mixture(ctx, np.asarray(m.K, np.int32), new_amp, np.asarray(m.var, np.float32))
+    ref = gfc.gfc_render_stamps(ctx, psf, mix2, gal.x, gal.y, gal.flux, gal.r_e, gal.e1, gal.e2, W)
+    torch.cuda.synchronize()
+    assert torch.equal(out.detach(), ref)
+    mix2.close()
     for i, tt in enumerate((x, y, fl)):
         assert torch.allclose(tt.grad, gp[:, i])
     assert torch.allclose(re.grad, gp[:, 3] / re.detach())
