@@ -430,6 +430,10 @@ def main():
     ap.add_argument("--no-probes", action="store_true", help="skip the device rate probes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (for scaling HBM counters)")
+    ap.add_argument("--profile-set", action="store_true",
+                    help="only launch every kernel instantiation a few times (for rocprofv3) and print "
+                         "their launch times")
+    ap.add_argument("--profile-reps", type=int, default=3)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -437,6 +441,24 @@ def main():
               "(stamps are independent, so more GPUs would each take a shard of the batch)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.profile_set:
+        import torch
+
+        import paper_2012_15797_amd as gfc
+
+        dev = torch.device("cuda", 0)
+        res = profile_set(gfc, gfc.Context.default(0), dev, args.profile_reps)
+        if args.copy_calibration:
+            a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+            b = torch.empty_like(a)
+            a.fill_(1.0)
+            torch.cuda.synchronize()
+            b.copy_(a)
+            torch.cuda.synchronize()
+            log("copy calibration: 1 GiB read + 1 GiB written")
+        print(json.dumps(dict(profile_set=res)), flush=True)
+        return
 
     cfg = wl.config_metric(args.n)
     gal = cfg["gal"]
@@ -578,6 +600,127 @@ def main():
                        min=round(float(kern_ms.min()), 4), max=round(float(kern_ms.max()), 4)),
     )
     print(json.dumps(rec), flush=True)
+
+
+def profile_set(gfc, ctx, dev, reps=3):
+    """Every kernel instantiation of the library, launched `reps` times after
+    one untimed launch, for rocprofv3 kernel traces and counters: the forward
+    render at 16, 32, 64, 128 and 256 (the throughput workload's galaxies,
+    radii scaled to the stamp; the large workload at 128 and 256), its
+    eigen-PSF, Lanczos (fused at 64, separate passes at 128 and 256), Sersic
+    and composite forms, the serving form with a per-galaxy PSF index, the
+    adjoint at every size with the amplitude sums, and the PSF transforms.
+    Returns the mean launch time of each case (HIP events)."""
+    import torch
+
+    d = lambda a: torch.as_tensor(a).to(dev)
+    res = {}
+
+    def run(name, n, fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[name] = dict(stamps=n, ms=round(ms, 4), stamps_per_s=round(n / ms * 1e3, 1))
+        log(f"profile set: {name}: {res[name]}")
+
+    cfg = wl.config_metric()
+    psf = gfc.Psf(ctx, cfg["psf"])
+    mix = gfc.Mixture.from_workload(ctx, cfg["mix"].as_f32())
+    rng = np.random.Generator(np.random.PCG64(8080))
+    for W, n in ((16, 200_000), (32, 100_000), (64, 100_000), (128, 20_000)):
+        g = wl.draw_galaxies(rng, n, W, 0, r_e_range=(0.5 * W / 64, 8.0 * W / 64))
+        args = [d(a) for a in (g.x, g.y, g.flux, g.r_e, g.e1, g.e2)]
+        out = torch.empty((n, W, W), dtype=torch.float32, device=dev)
+        psf.prepare(W)
+        run(f"forward-{W}", n, lambda: gfc.gfc_render_stamps(ctx, psf, mix, *args, W, out=out))
+        if W <= 128:
+            run(f"lanczos-{W}", n, lambda: gfc.gfc_render_stamps(ctx, psf, mix, *args, W, out=out,
+                                                                  flags=gfc.GFC_SHIFT_LANCZOS3))
+        nb = min(n, 20_000)
+        go = torch.randn((nb, W, W), device=dev, generator=torch.Generator(device=dev).manual_seed(W))
+        ba = [a[:nb] for a in args]
+        run(f"backward-{W}", nb, lambda: gfc.gfc_render_stamps_backward(ctx, psf, mix, *ba, W, go))
+        del out, go
+    c3 = wl.config3()
+    g = c3["gal"].subset(np.nonzero(c3["gal"].W == 256)[0])
+    psf3 = gfc.Psf(ctx, c3["psf"], c3.get("psf_gauss"))
+    args = [d(a) for a in (g.x, g.y, g.flux, g.r_e, g.e1, g.e2)]
+    out = torch.empty((len(g), 256, 256), dtype=torch.float32, device=dev)
+    psf3.prepare(256)
+    run("forward-256-large", len(g), lambda: gfc.gfc_render_stamps(ctx, psf3, mix, *args, 256, out=out))
+    run("lanczos-256-large", len(g), lambda: gfc.gfc_render_stamps(ctx, psf3, mix, *args, 256, out=out,
+                                                                  flags=gfc.GFC_SHIFT_LANCZOS3))
+    del out
+    nb = 2048
+    go = torch.randn((nb, 256, 256), device=dev, generator=torch.Generator(device=dev).manual_seed(256))
+    run("backward-256-large", nb, lambda: gfc.gfc_render_stamps_backward(ctx, psf3, mix, *[a[:nb] for a in args],
+                                                                           256, go))
+    del go
+    psf3.close()
+    # serving form: per-galaxy PSF index (requests of several PSFs fused), 64 x 64
+    from paper_2012_15797_amd.serving import Server
+    tr = wl.config4_trace(duration_s=0.05, rate_hz=2000.0, n_psf=8, restricted=False)
+    psfs = [gfc.Psf(ctx, p) for p in tr["psfs"][:8]]
+    tmix = gfc.Mixture.from_workload(ctx, tr["mix"].as_f32())
+    srv = Server(ctx, mem_budget_bytes=8 << 30, n_streams=1, max_batch_stamps=1 << 20)
+    g = wl.draw_galaxies(rng, 4096, 64, 0)
+
+    def served():
+        tk = [srv.submit(psfs[i % 8], tmix, 64, g.x[i::8], g.y[i::8], g.flux[i::8], g.r_e[i::8], g.e1[i::8],
+                         g.e2[i::8]) for i in range(8)]
+        for t in tk:
+            srv.wait(t)
+            srv.release(t)
+    run("serving-64-8psf", len(g), served)
+    srv.close()
+    for p in psfs:
+        p.close()
+    tmix.close()
+    # eigen-PSF, Sersic and composite forms at 64
+    ce = wl.config_eigen()
+    g, e = ce["gal"], ce["eig"]
+    epsf = gfc.Psf.eigen(ctx, e["comps"], e["coef"], e["degree"], e["norm"])
+    emix = gfc.Mixture.from_workload(ctx, ce["mix"].as_f32())
+    args = [d(a) for a in (g.x, g.y, g.flux, g.r_e, g.e1, g.e2)]
+    px, py = d(ce["psf_x"]), d(ce["psf_y"])
+    out = torch.empty((len(g), 64, 64), dtype=torch.float32, device=dev)
+    run("eigen-64", len(g), lambda: gfc.gfc_render_stamps(ctx, epsf, emix, *args, 64, out=out, psf_x=px, psf_y=py))
+    epsf.close()
+    emix.close()
+    cs = wl.config_sersic()
+    g = cs["gal"]
+    fam = gfc.SersicFamily.from_workload(ctx, cs["family"])
+    args = [d(a) for a in (g.x, g.y, g.flux, g.r_e, g.e1, g.e2)]
+    sn = d(cs["sersic_n"])
+    run("sersic-64", len(g), lambda: gfc.gfc_render_stamps_sersic(ctx, psf, fam, *args, sn, 64, out=out))
+    fam.close()
+    cc = wl.config_composite()
+    g = cc["gal"]
+    cmix = gfc.Mixture.from_workload(ctx, cc["mix"].as_f32())
+    args = [d(a) for a in (g.x, g.y, g.flux, g.r_e, g.e1, g.e2)]
+    fr, rh = d(cc["bulge_frac"]), d(cc["bulge_rho"])
+    run("composite-64", len(g), lambda: gfc.gfc_render_stamps_composite(ctx, psf, cmix, 0, 1, *args, fr, rh, 64,
+                                                                         out=out))
+    cmix.close()
+    del out
+    # the PSF transforms (cold path): a fresh PSF per launch, every size
+    P = cfg["psf"]
+
+    def transforms():
+        q = gfc.Psf(ctx, P)
+        for W in (16, 32, 64, 128, 256):
+            q.prepare(W)
+        q.close()
+    run("psf-transforms", 5, transforms)
+    psf.close()
+    mix.close()
+    return res
 
 
 def parity_of_rows(out, refs, dev):

@@ -7,19 +7,15 @@
 //   w[d] = L(d + f) / sum_d' L(d' + f),  L(t) = sinc(t) sinc(t / 3) on |t| < 3,
 // with pixels outside the stamp taken as zero.  Separable: rows, then columns.
 //
-// These passes serve W = 128 and 256 (up to 64 x 64 the render kernel
-// applies the same filter while it stores).  W = 128: one workgroup per
-// stamp, the stamp held in LDS, both passes in place, one read and one write
-// of the stamp.  W = 256 (256 KB per stamp): a row-band pass and a
-// column-band pass, each in place through LDS.
+// This pass serves W = 128 and 256 (up to 64 x 64 the render kernel applies
+// the same filter while it stores): one read and one write of the stamp,
+// in place.
 #include "gfc_internal.hpp"
 #include "gfc_launch.hpp"
 
 namespace gfc {
 
 namespace {
-
-constexpr int kThreads = 256;
 
 // Fills w[0..5] (taps d = -3..2) for the fractional part of v; lanes 0..11 of
 // the block compute the raw values, every lane normalises.
@@ -47,114 +43,51 @@ __device__ __forceinline__ void block_weights(float vx, float vy, float* s_w, fl
   }
 }
 
+// One workgroup of W threads per stamp, thread c owning column c.  It walks
+// down the stamp's rows once: row r is loaded (coalesced) and filtered along
+// x through a double-buffered LDS row with three zero pixels on each side;
+// the six most recent x-filtered rows stay in registers, and output row
+// r - 2 (taps r - 5 .. r) is stored as soon as row r is in.  The pass is in
+// place: a row is overwritten only after every thread has read it.  LDS is
+// two rows, so many workgroups share a CU and hide the memory latency.
 template <int W>
-__global__ void __launch_bounds__(kThreads) lanczos_tile_kernel(const float* __restrict__ x,
-                                                                const float* __restrict__ y, float* out) {
-  constexpr int TS = W + 1;
-  constexpr int PER = W * W / kThreads;  // pixels per thread
-  static_assert(W * W % kThreads == 0, "stamp size");
-  __shared__ float tile[W * TS];
+__global__ void __launch_bounds__(W) lanczos_stream_kernel(const float* __restrict__ x,
+                                                           const float* __restrict__ y, float* out) {
+  constexpr int PAD = 3;                 // zero pixels on each side of a row
+  __shared__ float row[2][W + 2 * PAD];
   __shared__ float s_w[12];
   const int64_t s = blockIdx.x;
   float* img = out + s * (int64_t)(W * W);
   float wx[6], wy[6];
   block_weights(x[s], y[s], s_w, wx, wy);
-  const int t = threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    const int i = t + k * kThreads;
-    tile[(i / W) * TS + (i % W)] = img[i];
+  const int c = threadIdx.x;
+  if (c < 2 * PAD) {  // the margins of both buffers
+    const int col = c < PAD ? c : W + c;
+    row[0][col] = 0.f;
+    row[1][col] = 0.f;
   }
-  __syncthreads();
-  float hv[PER];
+  float hw[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // x-filtered rows r - 5 .. r
+  float next = img[c];
+  for (int r = 0; r < W + 2; ++r) {
+    float h = 0.f;
+    if (r < W) {  // uniform
+      const float v = next;
+      if (r + 1 < W) next = img[(r + 1) * W + c];  // in flight during this row
+      float* b = row[r & 1];
+      b[PAD + c] = v;
+      __syncthreads();
 #pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    const int i = t + k * kThreads, r = i / W, c = i % W;
-    float acc = 0.f;
-#pragma unroll
-    for (int d = 0; d < 6; ++d) {
-      const int cc = c + d - 3;
-      if (cc >= 0 && cc < W) acc = fmaf(wx[d], tile[r * TS + cc], acc);
+      for (int d = 0; d < 6; ++d) h = fmaf(wx[d], b[c + d], h);
     }
-    hv[k] = acc;
-  }
-  __syncthreads();
 #pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    const int i = t + k * kThreads;
-    tile[(i / W) * TS + (i % W)] = hv[k];
-  }
-  __syncthreads();
+    for (int i = 0; i < 5; ++i) hw[i] = hw[i + 1];
+    hw[5] = h;
+    if (r >= 2) {
+      float o = 0.f;
 #pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    const int i = t + k * kThreads, r = i / W, c = i % W;
-    float acc = 0.f;
-#pragma unroll
-    for (int d = 0; d < 6; ++d) {
-      const int rr = r + d - 3;
-      if (rr >= 0 && rr < W) acc = fmaf(wy[d], tile[rr * TS + c], acc);
+      for (int j = 0; j < 6; ++j) o = fmaf(wy[j], hw[j], o);
+      __builtin_nontemporal_store(o, &img[(r - 2) * W + c]);
     }
-    __builtin_nontemporal_store(acc, &img[i]);
-  }
-}
-
-// W = 256: BAND rows (or columns) of one stamp per workgroup.
-constexpr int kW = 256;
-constexpr int BAND = 16;
-
-__global__ void __launch_bounds__(kThreads) lanczos_rows_kernel(const float* __restrict__ x,
-                                                                const float* __restrict__ y, float* out) {
-  __shared__ float tile[BAND * kW];
-  __shared__ float s_w[12];
-  const int64_t s = blockIdx.x / (kW / BAND);
-  const int r0 = (blockIdx.x % (kW / BAND)) * BAND;
-  float* img = out + s * (int64_t)(kW * kW) + r0 * kW;
-  float wx[6], wy[6];
-  block_weights(x[s], y[s], s_w, wx, wy);
-  const int t = threadIdx.x;  // = column
-#pragma unroll
-  for (int r = 0; r < BAND; ++r) tile[r * kW + t] = img[r * kW + t];
-  __syncthreads();
-#pragma unroll
-  for (int r = 0; r < BAND; ++r) {
-    float acc = 0.f;
-#pragma unroll
-    for (int d = 0; d < 6; ++d) {
-      const int cc = t + d - 3;
-      if (cc >= 0 && cc < kW) acc = fmaf(wx[d], tile[r * kW + cc], acc);
-    }
-    img[r * kW + t] = acc;
-  }
-}
-
-__global__ void __launch_bounds__(kThreads) lanczos_cols_kernel(const float* __restrict__ x,
-                                                                const float* __restrict__ y, float* out) {
-  constexpr int TS = BAND + 1;
-  __shared__ float tile[kW * TS];
-  __shared__ float s_w[12];
-  const int64_t s = blockIdx.x / (kW / BAND);
-  const int c0 = (blockIdx.x % (kW / BAND)) * BAND;
-  float* img = out + s * (int64_t)(kW * kW) + c0;
-  float wx[6], wy[6];
-  block_weights(x[s], y[s], s_w, wx, wy);
-  const int t = threadIdx.x;
-  const int cl = t % BAND, rq = t / BAND;  // 16 columns x 16 row phases
-#pragma unroll
-  for (int k = 0; k < kW / (kThreads / BAND); ++k) {
-    const int r = rq + k * (kThreads / BAND);
-    tile[r * TS + cl] = img[r * kW + cl];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < kW / (kThreads / BAND); ++k) {
-    const int r = rq + k * (kThreads / BAND);
-    float acc = 0.f;
-#pragma unroll
-    for (int d = 0; d < 6; ++d) {
-      const int rr = r + d - 3;
-      if (rr >= 0 && rr < kW) acc = fmaf(wy[d], tile[rr * TS + cl], acc);
-    }
-    __builtin_nontemporal_store(acc, &img[r * kW + cl]);
   }
 }
 
@@ -163,18 +96,13 @@ __global__ void __launch_bounds__(kThreads) lanczos_cols_kernel(const float* __r
 hipError_t launch_lanczos_shift(const RenderArgs& a, int W, hipStream_t stream) {
   constexpr int64_t kMaxBlocks = (int64_t)1 << 30;
   for (int64_t done = 0; done < a.n;) {
-    const int64_t per = (W == kW) ? (kW / BAND) : 1;  // workgroups per stamp
-    const int64_t chunk = std::min<int64_t>(a.n - done, kMaxBlocks / per);
+    const int64_t chunk = std::min<int64_t>(a.n - done, kMaxBlocks);
     const float* x = a.x + done;
     const float* y = a.y + done;
     float* o = a.out + done * (int64_t)W * W;
-    const dim3 grid((unsigned)(chunk * per)), block(kThreads);
     switch (W) {
-      case 128: hipLaunchKernelGGL(lanczos_tile_kernel<128>, grid, block, 0, stream, x, y, o); break;
-      case 256:
-        hipLaunchKernelGGL(lanczos_rows_kernel, grid, block, 0, stream, x, y, o);
-        hipLaunchKernelGGL(lanczos_cols_kernel, grid, block, 0, stream, x, y, o);
-        break;
+      case 128: hipLaunchKernelGGL(lanczos_stream_kernel<128>, dim3((unsigned)chunk), dim3(128), 0, stream, x, y, o); break;
+      case 256: hipLaunchKernelGGL(lanczos_stream_kernel<256>, dim3((unsigned)chunk), dim3(256), 0, stream, x, y, o); break;
       default: return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();

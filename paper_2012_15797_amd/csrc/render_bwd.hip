@@ -330,10 +330,14 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
 
   // ------------------------------------------------------------ component loop
   float ax = 0.f, ay = 0.f, a11 = 0.f, a12 = 0.f, a22 = 0.f;
-  // per-lane p_k partials [kKmax][W] in the g tile, which the column DFT has finished reading
+  // per-lane p_k partials [kKmax][W + 1] in the g tile, which the column DFT
+  // has finished reading.  Rows are W + 1 floats apart, so when lane k sums
+  // row k below, the 16 lanes read 16 different banks (at a row stride of W
+  // they all read one bank: about 240 conflict cycles per wavefront at 64).
+  constexpr int PKS = W + 1;
   float* s_pk = &s_tile[slot][0];
-  static_assert(kKmax * W <= C::TN, "p_k partials fit in the tile");
-  for (int k = 0; k < kKmax; ++k) s_pk[k * W + l] = 0.f;
+  static_assert(kKmax * PKS <= C::TN, "p_k partials fit in the tile");
+  for (int k = 0; k < kKmax; ++k) s_pk[k * PKS + l] = 0.f;
   static_for<0, (NP + C::PB - 1) / C::PB>([&](auto bb) {
     constexpr int b0 = decltype(bb)::value * C::PB;
     constexpr int nb = (NP - b0) < C::PB ? (NP - b0) : C::PB;
@@ -360,7 +364,7 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
         S1[j] = fmaf(wav, e, S1[j]);
         pk = fmaf(ure[b0 + j], e, pk);
       });
-      s_pk[k * W + l] += pk;
+      s_pk[k * PKS + l] += pk;
     }
     static_for<0, nb>([&](auto jj) {
       constexpr int j = decltype(jj)::value;
@@ -387,8 +391,8 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
   // p_k = sum over the stamp's lanes, fixed order; lane k of the stamp sums row k
   if (l < kKmax) {
     float acc = 0.f;
-    for (int i = 0; i < W; ++i) acc += s_pk[l * W + i];
-    s_pk[l * W] = acc;
+    for (int i = 0; i < W; ++i) acc += s_pk[l * PKS + i];
+    s_pk[l * PKS] = acc;
   }
   __syncthreads();
 
@@ -400,7 +404,7 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
     if constexpr (C::SPB == 1) make_uniform(Gc);
     CompTerms t = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (live && l < kKmax)
-      t = bwd_component_terms<W>(p, Gc, l, rmask, s_pk, W, &s_racc[slot][0][0], amp_part + gidx * kKmax);
+      t = bwd_component_terms<W>(p, Gc, l, rmask, s_pk, PKS, &s_racc[slot][0][0], amp_part + gidx * kKmax);
     t = sum16(t);
     if (l == 0 && live) bwd_chain_finish<W>(p, Gc, gidx, ax, ay, a11, a12, a22, t, grad_params);
   }
