@@ -33,7 +33,7 @@ SOURCES = [
     "sched.cpp",
     "render_dispatch.cpp",
     "render_fwd.hip",
-    "render_large.hip",
+    "render_w256.hip",
     "render_bwd.hip",
     "render_bwd_large.hip",
     "lanczos.hip",

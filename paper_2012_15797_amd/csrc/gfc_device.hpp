@@ -78,14 +78,24 @@ __device__ __forceinline__ bool finitef(float v) { return __builtin_isfinite(v);
 // Step 3: C_i = v_i B with B = A A^T, A = CD^{-1} E.  With c^2, s^2 and cs of
 // the position angle written through e1, e2 (Appendix A), E E^T is
 // r_e^2/(1+e)^2 [[1+e^2-2e1, 2e2], [2e2, 1+e^2+2e1]] -- no trigonometry.
+// A galaxy's inputs as they are stored.
+struct GalaxyIn {
+  float x, y, flux, re, e1, e2;
+  int table;
+};
+
+__device__ __forceinline__ GalaxyIn load_galaxy_in(const RenderArgs& p, int64_t g) {
+  return GalaxyIn{p.x[g], p.y[g], p.flux[g], p.r_e[g], p.e1[g], p.e2[g], p.mix_id ? p.mix_id[g] : 0};
+}
+
 template <int W>
-__device__ __forceinline__ Galaxy load_galaxy(const RenderArgs& p, int64_t g) {
+__device__ __forceinline__ Galaxy make_galaxy(const RenderArgs& p, const GalaxyIn& in) {
   Galaxy G;
-  G.x0 = p.x[g];
-  G.y0 = p.y[g];
-  G.flux = p.flux[g];
-  const float re = p.r_e[g], e1 = p.e1[g], e2 = p.e2[g];
-  G.table = p.mix_id ? p.mix_id[g] : 0;
+  G.x0 = in.x;
+  G.y0 = in.y;
+  G.flux = in.flux;
+  const float re = in.re, e1 = in.e1, e2 = in.e2;
+  G.table = in.table;
   const float esq = e1 * e1 + e2 * e2;
   G.ok = finitef(G.x0) && finitef(G.y0) && finitef(G.flux) && finitef(re) && finitef(e1) &&
          finitef(e2) && re > 0.f && esq < 1.f && fabsf(G.x0) <= 8388608.f &&
@@ -117,6 +127,27 @@ __device__ __forceinline__ Galaxy load_galaxy(const RenderArgs& p, int64_t g) {
   G.b12 = fmaf(p00, m10, p01 * m11);
   G.b22 = fmaf(p10, m10, p11 * m11);
   return G;
+}
+
+template <int W>
+__device__ __forceinline__ Galaxy load_galaxy(const RenderArgs& p, int64_t g) {
+  return make_galaxy<W>(p, load_galaxy_in(p, g));
+}
+
+// Fourier bins where a component's exponent (log2 of its share of the
+// component's amplitude) is below -kSkipLog2 may be skipped: every skipped
+// value is below 2^-40 of the amplitude, far under FP32 rounding of the stamp.
+constexpr float kSkipLog2 = 40.f;
+
+// A lower bound on the smallest eigenvalue of the galaxy's shape matrix B,
+// so that q(nu, omega) >= lambda (nu^2 + omega^2): the eigenvalue of the
+// FP32 matrix in double precision (no cancellation at any ellipticity),
+// less 0.1 per cent.
+__device__ __forceinline__ float shape_min_eig(const Galaxy& G) {
+  const double a = G.b11, b = G.b12, d = G.b22;
+  const double h = 0.5 * (a - d);
+  const double lam = 0.5 * (a + d) - sqrt(h * h + b * b);
+  return lam > 0.0 ? (float)(0.999 * lam) : 0.f;
 }
 
 __device__ __forceinline__ float uniform_f(float v) {
