@@ -156,8 +156,11 @@ __global__ void __launch_bounds__(w256::BLOCK) render_w256_kernel(RenderArgs pa)
     psfm = (GlobalF2)p.psf_main_tab[ps];
     psfn = (GlobalF2)p.psf_nyq_tab[ps];
   }
-  const float* amp = p.amp + G.table * kKmax;
-  const float* var = p.var + G.table * kKmax;
+  // The mixture tables are read-only during the launch: constant address
+  // space, so the uniform reads are scalar loads.
+  typedef const __attribute__((address_space(4))) float* ConstF;
+  ConstF amp = (ConstF)p.amp + G.table * kKmax;
+  ConstF var = (ConstF)p.var + G.table * kKmax;
   const float trB = G.b11 + G.b22;
   const float fs = G.flux * (1.f / ((float)W * (float)W));
 
@@ -233,9 +236,16 @@ __global__ void __launch_bounds__(w256::BLOCK) render_w256_kernel(RenderArgs pa)
   int wvs = wv;  // renewed per stamp: the bounds below are not held across stamps
   asm volatile("" : "+s"(wvs));
   const float nlo = (float)(8 * wvs) * (1.f / W);
-  const float r2[4] = {uniform_f(nlo * nlo), uniform_f(fmaf(nlo, nlo, 0.0625f)),
-                       uniform_f(fmaf(nlo, nlo, (65.f * 65.f) / (256.f * 256.f))),
-                       uniform_f(fmaf(nlo, nlo, 1.f / (256.f * 256.f)))};
+  // A component of variance v is evaluated in block b when v < vmax[b]
+  // (vmax = +inf when lambda or the radius is zero).
+  const float r2[4] = {nlo * nlo, fmaf(nlo, nlo, 0.0625f), fmaf(nlo, nlo, (65.f * 65.f) / (256.f * 256.f)),
+                       fmaf(nlo, nlo, 1.f / (256.f * 256.f))};
+  float vmax[4];
+  static_for<0, 4>([&](auto bb) {
+    constexpr int b = decltype(bb)::value;
+    vmax[b] = uniform_f(kSkipLog2 / (lamq * r2[b]));
+  });
+  const float vmaxN = uniform_f(kSkipLog2 / (lamq * 0.25f));  // |nu| = 1/2 or |omega| = 1/2
   float S[M];
   float SN[3] = {0.f, 0.f, 0.f};
   static_for<0, M>([&](auto mm) { S[decltype(mm)::value] = 0.f; });
@@ -250,17 +260,16 @@ __global__ void __launch_bounds__(w256::BLOCK) render_w256_kernel(RenderArgs pa)
     }
     const float wa = w * A;
     if (wa == 0.f) continue;
-    const float sk = uniform_f(v * lamq);
     static_for<0, M / 8>([&](auto bb) {
       constexpr int b = decltype(bb)::value;
-      if (sk * r2[b] < kSkipLog2) {
+      if (v < vmax[b]) {
         static_for<0, 8>([&](auto ii) {
           constexpr int m = 8 * b + decltype(ii)::value;
           S[m] = fmaf(wa, __builtin_amdgcn_exp2f(v * qv[m]), S[m]);
         });
       }
     });
-    if (nyq && sk * 0.25f < kSkipLog2) {  // |nu| = 1/2 or |omega| = 1/2
+    if (nyq && v < vmaxN) {
       SN[0] = fmaf(wa, __builtin_amdgcn_exp2f(v * qn[0]), SN[0]);
       SN[1] = fmaf(wa, __builtin_amdgcn_exp2f(v * qn[1]), SN[1]);
       if (twin) SN[2] = fmaf(wa, __builtin_amdgcn_exp2f(v * qn[2]), SN[2]);
