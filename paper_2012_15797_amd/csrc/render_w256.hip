@@ -47,6 +47,9 @@ constexpr int TS = 130;
 // S = 2 (mod 16): writes 2 y' + r, reads 2 y' + 9 r.
 constexpr int CXS = 72;
 constexpr int RXS = 82;
+// Row stride of the combine twiddle table (float2): odd, so rows h start in
+// distinct banks.
+constexpr int TWC = 33;
 constexpr int LDS_F2 = HROWS * TS;  // 133 KB
 static_assert(NWAVE * 8 * CXS <= LDS_F2 && NWAVE * 8 * RXS <= LDS_F2, "the exchange slices alias the half buffer");
 }  // namespace w256
@@ -116,11 +119,19 @@ __global__ void __launch_bounds__(w256::BLOCK) render_w256_kernel(RenderArgs pa)
   __shared__ float2 s_py[W + 2];
   __shared__ float2 s_nyq[W];
   __shared__ float s_tw[NC];        // the Nyquist row's omega = -1/2 twin, per column
-  __shared__ float2 s_rs[kKmax];    // (v, (1 - w) A) of the components with a real-space share
+  __shared__ float4 s_rc[kKmax];    // real-space components: amplitude, g, sxy / syy, -log2(e) / (2 syy)
+  // Combine twiddles s_twc[h][8 k + g] = w^(g (8 k + h)), w = exp(2 pi i /
+  // 256), rows TWC apart so that a 16-lane group's reads fall in distinct
+  // banks.
+  __shared__ float2 s_twc[8 * TWC];
   __shared__ float s_cj[kEigMax];   // eigen-PSF component weights at this galaxy's position
   __shared__ uint32_t s_in[kInWords];
 
   if (threadIdx.x < kInWords) s_in[threadIdx.x] = stamp_word<EIG, PT>(pa, blockIdx.x, threadIdx.x);
+  if (threadIdx.x < 256) {
+    const int hh = threadIdx.x >> 5, kg = threadIdx.x & 31;  // kg = 8 k + g
+    s_twc[hh * TWC + kg] = twiddle_rt<+1, W>((kg & 7) * (8 * (kg >> 3) + hh));
+  }
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wavefront index (scalar)
   for (int64_t stamp = blockIdx.x; stamp < pa.n; stamp += gridDim.x) {
   const RenderArgs& p = kernel_args_renewed<RenderArgs>();
@@ -256,7 +267,18 @@ __global__ void __launch_bounds__(w256::BLOCK) render_w256_kernel(RenderArgs pa)
     const float w = route_weight<W>(v * trB, p.flags);
     if (w < 1.f && A != 0.f) {
       rmask |= 1u << k;
-      if (t == 0) s_rs[k] = make_float2(v, (1.f - w) * A);
+      if (t == 0) {
+        // the component convolved with the PSF Gaussian: covariance
+        // v B + C_p, amplitude (1 - w) A flux a_p / (2 pi sqrt(det))
+        const float sxx = fmaf(v, G.b11, pg[2]);
+        const float sxy = fmaf(v, G.b12, pg[3]);
+        const float syy = fmaf(v, G.b22, pg[4]);
+        const float det = fmaf(sxx, syy, -(sxy * sxy));
+        const float rsyy = __builtin_amdgcn_rcpf(syy);
+        s_rc[k] = make_float4((1.f - w) * A * G.flux * pg[5] * kInv2Pi * __builtin_amdgcn_rsqf(det),
+                              sqrtf(-kHalfLog2e * syy * __builtin_amdgcn_rcpf(det)), sxy * rsyy,
+                              kHalfLog2e * rsyy);
+      }
     }
     const float wa = w * A;
     if (wa == 0.f) continue;
@@ -387,18 +409,12 @@ __global__ void __launch_bounds__(w256::BLOCK) render_w256_kernel(RenderArgs pa)
         a[g] = cxb[9 * h + g];
       });
       wave_lds_sync();  // read before the next chunk overwrites the slot
-      // w^(g j), w = exp(2 pi i / 256): g = 1..4 from the table, 5..7 as
-      // products of two
-      const int j = 8 * k + h;
-      const float2 w1 = twiddle_rt<+1, W>(j), w2 = twiddle_rt<+1, W>(2 * j);
-      const float2 w3 = twiddle_rt<+1, W>(3 * j), w4 = twiddle_rt<+1, W>(4 * j);
-      a[1] = cmul(a[1], w1);
-      a[2] = cmul(a[2], w2);
-      a[3] = cmul(a[3], w3);
-      a[4] = cmul(a[4], w4);
-      a[5] = cmul(a[5], cmul(w4, w1));
-      a[6] = cmul(a[6], cmul(w4, w2));
-      a[7] = cmul(a[7], cmul(w4, w3));
+      // w^(g j), j = 8 k + h
+      const float2* tw = s_twc + h * TWC + 8 * k;
+      static_for<1, 8>([&](auto gg) {
+        constexpr int g = decltype(gg)::value;
+        a[g] = cmul(a[g], tw[g]);
+      });
       fft<8, +1>(a);
       static_for<0, 8>([&](auto qq) { X4[k][decltype(qq)::value] = a[decltype(qq)::value]; });
     });
@@ -436,7 +452,7 @@ __global__ void __launch_bounds__(w256::BLOCK) render_w256_kernel(RenderArgs pa)
     float2 R[16];
     {
       const float2* row = s_buf + yloc * TS;
-      const float2 wr = twiddle_rt<+1, W>(r);
+      const float2 wr = s_twc[r * TWC + 1];  // w^r
       static_for<0, 16>([&](auto mm) {
         constexpr int m = decltype(mm)::value;
         const int k = 8 * m + r;
@@ -491,21 +507,13 @@ __global__ void __launch_bounds__(w256::BLOCK) render_w256_kernel(RenderArgs pa)
       const float dy = (float)y - G.y0 - pg[1];
       const float dx0 = -G.x0 - pg[0];  // dx of column 0
       for (unsigned mk = rmask; mk != 0; mk &= mk - 1) {
-        const float2 rs = s_rs[__builtin_ctz(mk)];
-        const float v = rs.x, ra = rs.y;
-        const float sxx = fmaf(v, G.b11, pg[2]);
-        const float sxy = fmaf(v, G.b12, pg[3]);
-        const float syy = fmaf(v, G.b22, pg[4]);
-        const float det = fmaf(sxx, syy, -(sxy * sxy));
-        const float rdet = __builtin_amdgcn_rcpf(det);
-        const float ampr = ra * G.flux * pg[5] * kInv2Pi * __builtin_amdgcn_rsqf(det);
+        const float4 rc = s_rc[__builtin_ctz(mk)];
+        const float ampr = rc.x, g = rc.y;
         // along the row (dy fixed) the quadratic form is dy^2 / syy +
         // (syy / det) (dx - (sxy / syy) dy)^2, completed about the conditional
         // mean: with dx = x + dx0 the exponent is k - u^2, u = g (x + m)
-        const float rsyy = __builtin_amdgcn_rcpf(syy);
-        const float g = sqrtf(-kHalfLog2e * syy * rdet);
-        const float k0 = kHalfLog2e * dy * dy * rsyy;
-        const float gm = g * fmaf(-sxy * rsyy, dy, dx0 + (float)(4 * r));  // x measured from this lane's 4 r
+        const float k0 = rc.w * dy * dy;
+        const float gm = g * fmaf(-rc.z, dy, dx0 + (float)(4 * r));  // x measured from this lane's 4 r
         static_for<0, 8>([&](auto qq) {
           constexpr int q = decltype(qq)::value;
           constexpr float xo = (float)(32 * q);
