@@ -84,6 +84,42 @@ def algorithmic_flops_per_stamp(W, kf, kr):
     return n_eval * (4.0 + 4.0 * kf) + 14.0 * H + 2.5 * W * W * math.log2(W * W) + 7.0 * W * W * kr
 
 
+def adjoint_flops_per_stamp(W, kf, kr):
+    """FLOPs the adjoint needs per stamp (FMA = 2, exp = 1): the real-to-complex
+    2-D transform of the upstream gradient (2.5 W^2 log2 W^2); per evaluation
+    point the PSF x phase x conj(G) product (14) and the parameter sums from
+    the bin's S and S1 (19: flux, two positions, three shape entries); per
+    Fourier component and point an exponential, its scale and three
+    accumulations (S, S1, the component's own sum: 8); per real-space
+    component and pixel the value and the six parameter accumulations (11)."""
+    H = W * (W // 2 + 1)
+    n_eval = H + (W // 2 + 1) + W + 2
+    return n_eval * (19.0 + 8.0 * kf) + 14.0 * H + 2.5 * W * W * math.log2(W * W) + 11.0 * W * W * kr
+
+
+def workload_flops(gal, mix, W, adjoint=False):
+    """Algorithmic FLOPs of one launch over `gal` (stamp size W), from each
+    galaxy's routing counts under its own mixture table."""
+    mid = np.asarray(gal.mix_id) if getattr(gal, "mix_id", None) is not None else np.zeros(len(gal.x), np.int32)
+    mid = np.broadcast_to(mid, (len(gal.x),))
+    f = adjoint_flops_per_stamp if adjoint else algorithmic_flops_per_stamp
+    total = 0.0
+    for t in np.unique(mid):
+        sel = np.nonzero(mid == t)[0]
+        k = int(mix.K[t])
+        kf, kr = routing_counts(gal.subset(sel), np.asarray(mix.var[t, :k], np.float64), W)
+        total += float(f(W, kf, kr).sum())
+    return total
+
+
+def flops_roofline(flops, ms):
+    """Achieved TFLOP/s of a launch and its fraction of the FP32 FMA peak
+    without packed instructions."""
+    tf = flops / (ms * 1e-3) / 1e12
+    return dict(bound="alu", achieved_tflops=round(tf, 3), peak_tflops=round(FP32_FMA_NONPACKED_TFLOPS, 2),
+                frac=round(tf / FP32_FMA_NONPACKED_TFLOPS, 4), flops_per_launch=round(flops, 1))
+
+
 def algorithmic_issue_slots(W, kf, kr):
     """(VALU issue slots, exponentials) per stamp of the same algorithm when
     every FMA-able pair is one instruction: quadratic form 2 per evaluation
@@ -835,7 +871,8 @@ def size_throughput(gfc, ctx, dev, refs, reps=5):
                 rows = out[torch.as_tensor(pos, device=dev)].cpu().numpy().astype(np.float64)
                 par = stamp_parity(rows, [ref[j] for j, _ in keep])
                 worst.append(par)
-            res[f"{cname}/W{W}"] = line(len(sub), ms, parity=par)
+            res[f"{cname}/W{W}"] = line(len(sub), ms, parity=par,
+                                        roofline=flops_roofline(workload_flops(sub, cfg["mix"], W), ms))
             tot_ms += ms
             tot_n += len(sub)
             del out
@@ -921,7 +958,8 @@ def size_throughput(gfc, ctx, dev, refs, reps=5):
         par = dict(n_checked=int(len(ii)), max_rel_err=float(rel.max()), max_err_over_bound=float(
             (np.abs(got - ref) / bound).max()), tol="1e-4 relative where |oracle| >= 1e-2 rms, else + 1e-5 rms",
                    passed=bool((np.abs(got - ref) <= bound).all()))
-    res["backward-dev8-64x64-10k"] = line(len(g), ms, parity=par)
+    res["backward-dev8-64x64-10k"] = line(len(g), ms, parity=par,
+                                          roofline=flops_roofline(workload_flops(g, cfg["mix"], 64, adjoint=True), ms))
     psf.close()
     mix.close()
     return res
