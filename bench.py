@@ -17,12 +17,16 @@ Order of a run:
      of the workload (cpu_baseline); the same processes then compute, untimed,
      the reference samples that gate every other reported number.
   2. Rate probes of the device (FMA, v_exp_f32, HBM write and copy): the
-     measured roofline denominators.  They also bring the clocks up.
-  3. W warm-up steps, then K timed steps (HIP events on the launch stream).
+     measured roofline denominators.
+  3. Settle steps (default 45): a fresh GPU under this full load runs a few
+     launches fast, is then throttled by its power management (about 0.75
+     ms per launch instead of 0.52) and reaches steady clocks after about 40
+     launches.  These untimed steps carry it through that transient, then W
+     warm-up steps, then K timed steps (HIP events on the launch stream).
   4. Parity of the timed output, the plain per-request launches, serving,
      and the other workloads, each with a parity record from its own launch.
 
-    python bench.py [--gpus 1] [--steps 100] [--warmup 30]
+    python bench.py [--gpus 1] [--steps 100] [--warmup 30] [--settle 45]
 """
 
 from __future__ import annotations
@@ -454,6 +458,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--settle", type=int, default=45,
+                    help="untimed steps before the warm-up that carry the device through its power-management "
+                         "transient (a fast start, a throttled stretch, then steady clocks after about 40 full-load "
+                         "launches); reported as settle_steps")
     ap.add_argument("--n", type=int, default=100_000)
     ap.add_argument("--cpu-sample", type=int, default=20000)
     ap.add_argument("--cpu-workers", type=int, default=0)
@@ -535,10 +543,17 @@ def main():
     def step():
         gfc.gfc_render_stamps(ctx, psf, mix, x, y, fl, re, e1, e2, W, out=out)
 
+    # Settle: a full-load launch sequence on a freshly started GPU runs fast for
+    # a few launches, is then throttled (about 0.75 ms per 64x64 launch instead
+    # of 0.52) and recovers over about 40 launches.  These untimed steps carry
+    # the device through that transient, so the timed steps measure the steady
+    # state at any --warmup.
+    for _ in range(args.settle):
+        step()
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    log(f"warmup done ({args.warmup} steps)")
+    log(f"settle ({args.settle} steps) and warmup ({args.warmup} steps) done")
 
     stream = torch.cuda.current_stream(dev)     # the stream the library launches on
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -557,6 +572,7 @@ def main():
     avg_kern_ms = float(kern_ms.mean())
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step, kernel mean {avg_kern_ms:.3f} ms, "
         f"median {np.median(kern_ms):.3f}, min {kern_ms.min():.3f}")
+    log("kernel ms per timed step: " + " ".join(f"{v:.3f}" for v in kern_ms))
 
     flops_launch = float(flops_stamp.sum())
     achieved_tflops = flops_launch / (avg_kern_ms * 1e-3) / 1e12
@@ -623,7 +639,7 @@ def main():
 
     rec = dict(
         metric=METRIC, value=round(value, 1), unit="stamps/s", n_gpus=1, steps=args.steps,
-        warmup=args.warmup, ms_per_step=round(ms_per_step, 4), higher_is_better=True,
+        warmup=args.warmup, settle_steps=args.settle, ms_per_step=round(ms_per_step, 4), higher_is_better=True,
         scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
         config=dict(workload="dev8-64x64-moffat-100k", n_stamps=args.n, W=W, K=8,
                     mixture="DEV8 synthetic (Dirichlet amplitudes, variances logspace 1e-4..10 r_e^2)",
