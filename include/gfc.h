@@ -15,6 +15,11 @@
  *   - All functions return gfc_status (0 = OK, < 0 = error).  No C++
  *     exception crosses the ABI.  On error a message is available from
  *     gfc_last_error() on the calling thread.
+ *   - With GFC_LOG=1 in the environment (read once), errors and the
+ *     library's events (PSF-FT cache fills, render calls, server
+ *     submissions, batch launches and completions) are also written to
+ *     stderr as JSON lines {"t": seconds, "event": name, ...}.  The host side
+ *     of those steps carries roctx ranges for rocprofv3 --marker-trace.
  *   - "device" pointers are HIP device allocations on the context's device;
  *     "host" pointers are ordinary host memory.  Host inputs are copied
  *     before the call returns; the caller keeps ownership of everything it

@@ -65,9 +65,9 @@ def _compile(src: str, obj: str) -> None:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
 
 
-def _link(objs, path):
+def _link(objs, path, libs=()):
     tmp = path + ".tmp"
-    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lpthread"]
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, *libs, "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -87,7 +87,9 @@ def build_library(verbose: bool = False, jobs: int = 8) -> str:
         futs = [ex.submit(_compile, os.path.join(CSRC, s), o) for s, o in objs.items()]
         for f in futs:
             f.result()
-    _link([objs[s] for s in SOURCES], LIB_PATH)
+    # roctx ranges of the host side (rocprofiler-sdk's roctx library)
+    _link([objs[s] for s in SOURCES], LIB_PATH, ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx",
+                                                 "-Wl,-rpath,/opt/rocm/lib"])
     _link([objs[s] for s in MB_SOURCES], MB_LIB_PATH)
     if verbose:
         print(f"built {LIB_PATH} from {len(SOURCES)} sources and {MB_LIB_PATH}")

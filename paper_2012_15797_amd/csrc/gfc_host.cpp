@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -14,6 +15,7 @@
 #include "gfc.h"
 #include "gfc_internal.hpp"
 #include "gfc_launch.hpp"
+#include "gfc_trace.hpp"
 
 using gfc::RenderArgs;
 
@@ -41,6 +43,8 @@ gfc_status psf_cache(gfc_psf* psf, int W, hipStream_t stream, const PsfSpectrum*
     *out = &it->second;
     return GFC_OK;
   }
+  TraceScope trace("gfc psf cache fill");
+  const auto t0 = std::chrono::steady_clock::now();
   PsfSpectrum spec;
   const size_t main_n = (size_t)(W / 2) * W, nyq_n = (size_t)W;
   const int ncomp = psf->J > 0 ? psf->J : 1;
@@ -69,6 +73,11 @@ gfc_status psf_cache(gfc_psf* psf, int W, hipStream_t stream, const PsfSpectrum*
   spec.W = W;
   auto ins = psf->cache.emplace(W, spec);
   *out = &ins.first->second;
+  if (log_enabled())
+    log_event("psf_cache_fill", "\"psf\": " + std::to_string(psf->uid) + ", \"W\": " + std::to_string(W) +
+                                    ", \"components\": " + std::to_string(ncomp) + ", \"ms\": " +
+                                    std::to_string(std::chrono::duration<double, std::milli>(
+                                                       std::chrono::steady_clock::now() - t0).count()));
   return GFC_OK;
 }
 
@@ -502,6 +511,7 @@ gfc_status gfc_mix_destroy(gfc_mix* mix) {
 
 gfc_status gfc_render_stamps(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix* mix, const gfc_galaxies* gal,
                              int64_t n, int W, unsigned flags, float* out, void* hip_stream) {
+  TraceScope trace("gfc render");
   RenderArgs a;
   gfc_status st = fill_render_args(ctx, psf, mix, gal, n, W, flags, &a);
   if (st != GFC_OK) return st;
@@ -514,6 +524,9 @@ gfc_status gfc_render_stamps(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix* mix, con
   if (st != GFC_OK) return st;
   attach_spectrum(&a, spec);
   a.out = out;
+  if (log_enabled())
+    log_event("render", "\"n\": " + std::to_string(n) + ", \"W\": " + std::to_string(W) + ", \"flags\": " +
+                            std::to_string(flags));
   return render_launch(a, W, s);
 }
 

@@ -27,6 +27,7 @@
 #include "gfc_internal.hpp"
 #include "gfc_launch.hpp"
 #include "bwd_common.hpp"
+#include "gfc_trace.hpp"
 
 namespace gfc {
 
@@ -608,6 +609,7 @@ gfc_status gfc_render_stamps_backward(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix*
                                       int64_t n, int W, unsigned flags, const float* grad_out,
                                       float* grad_params, float* grad_amp, void* workspace,
                                       void* hip_stream) {
+  TraceScope trace("gfc render backward");
   if (psf && psf->J > 0) return fail(GFC_EUNSUPPORTED, "the adjoint takes a constant PSF");
   if (flags & GFC_SHIFT_LANCZOS3) return fail(GFC_EUNSUPPORTED, "the adjoint uses the Fourier-phase shift");
   if (flags & GFC_ACCUMULATE) return fail(GFC_EINVAL, "GFC_ACCUMULATE applies to forward renders");

@@ -27,6 +27,7 @@
 
 #include "gfc_internal.hpp"
 #include "gfc_launch.hpp"
+#include "gfc_trace.hpp"
 #include "sched_core.hpp"
 
 namespace gfc {
@@ -38,6 +39,7 @@ struct HipBatch : BatchState {
   hipEvent_t event = nullptr;
   std::vector<hipEvent_t> reads;         // copies out of `mem` on callers' streams (gfc_server_copy)
   size_t arena_off = 0, arena_size = 0;  // `mem` is arena_size bytes of the arena (0: its own allocation)
+  std::chrono::steady_clock::time_point t_launch;
 };
 
 static HipBatch& hb(Batch& b) {
@@ -147,6 +149,7 @@ class HipExecutor : public Executor {
     return GFC_OK;
   }
   int launch(Batch& b) override {
+    TraceScope trace("gfc batch launch");
     DeviceGuard g(ctx_->device);
     Req* r0 = b.reqs.front();
     const int W = r0->W;
@@ -210,13 +213,25 @@ class HipExecutor : public Executor {
     h.event = events_[b.stream];
     if (hipEventRecord(h.event, s) != hipSuccess) return fail_batch(b);
     for (Req* r : b.reqs) r->out_ptr = dout + r->offset * (int64_t)W * W;
+    h.t_launch = std::chrono::steady_clock::now();
+    if (log_enabled())
+      log_event("batch_launch", "\"batch\": " + std::to_string(b.id) + ", \"requests\": " +
+                                    std::to_string(b.reqs.size()) + ", \"stamps\": " + std::to_string(n) +
+                                    ", \"W\": " + std::to_string(W) + ", \"stream\": " + std::to_string(b.stream));
     return 0;
   }
   int poll(Batch& b) override {
     HipBatch& h = hb(b);
     if (!h.event) return -1;
     const hipError_t e = hipEventQuery(h.event);
-    if (e == hipSuccess) return 1;
+    if (e == hipSuccess) {
+      trace_mark("gfc batch complete");
+      if (log_enabled())
+        log_event("batch_complete", "\"batch\": " + std::to_string(b.id) + ", \"ms\": " +
+                                        std::to_string(std::chrono::duration<double, std::milli>(
+                                                           std::chrono::steady_clock::now() - h.t_launch).count()));
+      return 1;
+    }
     if (e == hipErrorNotReady) return 0;
     return -1;
   }
@@ -376,6 +391,7 @@ gfc_status gfc_server_create(gfc_ctx* ctx, size_t mem_budget_bytes, int n_stream
 }
 
 gfc_status gfc_server_submit(gfc_server* s, const gfc_request* q, uint64_t* ticket) {
+  TraceScope trace("gfc server submit");
   if (!s || !q || !ticket) return fail(GFC_EINVAL, "null argument");
   if (!q->psf || !q->mix || q->psf->ctx != s->ctx || q->mix->ctx != s->ctx)
     return fail(GFC_EINVAL, "request PSF or mixture missing or from another context");
@@ -405,7 +421,12 @@ gfc_status gfc_server_submit(gfc_server* s, const gfc_request* q, uint64_t* tick
   const float* src[6] = {q->x, q->y, q->flux, q->r_e, q->e1, q->e2};
   for (int f = 0; f < 6; ++f) std::memcpy(r->params.data() + (size_t)f * q->n, src[f], q->n * sizeof(float));
   if (q->mix_id) r->mix_id.assign(q->mix_id, q->mix_id + q->n);
-  return s->loop->submit(std::move(r), ticket);
+  const int slot = r->psf_slot;
+  const gfc_status st = s->loop->submit(std::move(r), ticket);
+  if (st == GFC_OK && log_enabled())
+    log_event("server_submit", "\"ticket\": " + std::to_string(*ticket) + ", \"stamps\": " + std::to_string(q->n) +
+                                   ", \"W\": " + std::to_string(q->W) + ", \"psf_slot\": " + std::to_string(slot));
+  return st;
 }
 
 gfc_status gfc_server_poll(gfc_server* s, uint64_t ticket, int* done, const float** out_dev,

@@ -58,3 +58,27 @@ def test_rate_probe_library_exports_its_header():
 
     lib = ctypes.CDLL(os.path.join(ROOT, "paper_2012_15797_amd", "libgfc_microbench.so"))
     assert all(hasattr(lib, n) for n in names)
+
+
+def test_gfc_log_writes_json_lines():
+    """GFC_LOG=1: a failing call writes one JSON line (event "error", its
+    status and message) to stderr; without it nothing is written."""
+    import json
+    import subprocess
+    import sys
+
+    lib = os.path.join(ROOT, "paper_2012_15797_amd", "libgfc.so")
+    code = ("import ctypes, sys\n"
+            "lib = ctypes.CDLL(sys.argv[1])\n"
+            "lib.gfc_server_submit.restype = ctypes.c_int\n"
+            "print(lib.gfc_server_submit(None, None, None))\n")
+    env = dict(os.environ, GFC_LOG="1")
+    r = subprocess.run([sys.executable, "-c", code, lib], env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    lines = [json.loads(ln) for ln in r.stderr.splitlines() if ln.startswith("{")]
+    errs = [ln for ln in lines if ln["event"] == "error"]
+    assert len(errs) == 1 and errs[0]["status"] == int(r.stdout.strip()) and "null" in errs[0]["message"]
+    assert isinstance(errs[0]["t"], float)
+    env.pop("GFC_LOG")
+    r = subprocess.run([sys.executable, "-c", code, lib], env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and not [ln for ln in r.stderr.splitlines() if ln.startswith("{")], r.stderr

@@ -150,10 +150,10 @@ def test_large_galaxy_workload(ctx, W):
 
 def test_large_workload_full_size_sampled(ctx):
     """Every 256 x 256 stamp of the large-galaxy workload (about 9,900) in one
-    launch, as the benchmark times it: workgroups stay resident and take
-    several stamps each, one scratch slab per workgroup.  Stamps at the first
-    and later rounds of the workgroups, the last stamp and a random sample
-    against the oracle; every stamp finite."""
+    launch, as the benchmark times it: one workgroup per CU stays resident
+    and takes stamps in turn.  Stamps at the first and later rounds of the
+    workgroups, the last stamp and a random sample against the oracle; every
+    stamp finite."""
     import torch
     import paper_2012_15797_amd as gfc
 
@@ -169,6 +169,45 @@ def test_large_workload_full_size_sampled(ctx):
     idx = sorted(set([0, 1, 255, 256, 257, 511, 512, 1023, 1024, n - 1]) |
                  set(rng.choice(n, 14, replace=False).tolist()))
     sample = out[torch.as_tensor(idx, device=out.device)].cpu().numpy().astype(np.float64)
+    errs = peak_errors(sample, oracle_stamps(cfg, gal, idx), list(range(len(idx))))
+    assert errs.max() <= TOL_PEAK, errs.max()
+    psf.close(); mix.close()
+
+
+def test_w256_persistent_rounds_tables_and_invalid():
+    """At 256 x 256 a workgroup takes stamps in turn and loads the next
+    stamp's inputs while it renders the current one.  600 galaxies (two to
+    three stamps per workgroup) alternate between two mixture tables, with
+    invalid galaxies in the first, second and third rounds: those come out
+    NaN and are counted, and their neighbours, whose inputs travel beside
+    them, match the oracle."""
+    import torch
+    import paper_2012_15797_amd as gfc
+
+    local = gfc.Context(0)
+    cfg = wl.config2(10)  # two tables (EXP6 and DEV8) and the Moffat + halo PSF
+    rng = np.random.Generator(np.random.PCG64(256))
+    n = 600
+    g = wl.draw_galaxies(rng, n, 256, (np.arange(n) % 2).astype(np.int32), r_e_range=(4.0, 40.0))
+    x, r_e, e1, e2, mid = g.x.copy(), g.r_e.copy(), g.e1.copy(), g.e2.copy(), g.mix_id.copy()
+    e1[5], e2[5] = 0.99, 0.5  # |e| >= 1
+    r_e[256] = -1.0
+    mid[300] = 7              # no such table
+    x[599] = np.nan
+    bad = [5, 256, 300, 599]
+    gal = wl.Galaxies(x, g.y, g.flux, r_e, e1, e2, mid, g.W)
+    psf, mix = lib_objects(local, cfg)
+    out = gfc.gfc_render_stamps(local, psf, mix, gal.x, gal.y, gal.flux, gal.r_e, gal.e1, gal.e2, 256,
+                                mix_id=gal.mix_id)
+    torch.cuda.synchronize()
+    dev = out.device
+    assert torch.isnan(out[torch.as_tensor(bad, device=dev)]).all()
+    good = torch.as_tensor([i for i in range(n) if i not in bad], device=dev)
+    assert torch.isfinite(out[good]).all()
+    assert local.invalid_count() == len(bad)
+    idx = sorted(set([0, 4, 6, 255, 257, 299, 301, 511, 512, 598]) |
+                 set(int(i) for i in rng.choice([i for i in range(n) if i not in bad], 3, replace=False)))
+    sample = out[torch.as_tensor(idx, device=dev)].cpu().numpy().astype(np.float64)
     errs = peak_errors(sample, oracle_stamps(cfg, gal, idx), list(range(len(idx))))
     assert errs.max() <= TOL_PEAK, errs.max()
     psf.close(); mix.close()

@@ -246,3 +246,40 @@ def test_release_right_after_copy_keeps_the_copy(ctx):
     for p in psfs:
         p.close()
     mix.close()
+
+
+def test_gfc_log_traces_a_served_request():
+    """With GFC_LOG=1 a served run writes JSON lines: the PSF's cache fill,
+    each submission, each batch launch (its requests and stamps) and its
+    completion.  Run in a child process, since the setting is read once."""
+    import json
+    import os
+    import subprocess
+    import sys
+
+    code = r'''
+import numpy as np, workloads as wl, paper_2012_15797_amd as gfc
+from paper_2012_15797_amd.serving import Server
+ctx = gfc.Context.default(0)
+cfg = wl.config_metric(10)
+psf = gfc.Psf(ctx, cfg["psf"]); mix = gfc.Mixture.from_workload(ctx, cfg["mix"].as_f32())
+srv = Server(ctx, mem_budget_bytes=1 << 30, n_streams=1)
+g = cfg["gal"]
+ts = [srv.submit(psf, mix, 64, g.x[i::2], g.y[i::2], g.flux[i::2], g.r_e[i::2], g.e1[i::2], g.e2[i::2]) for i in range(2)]
+for t in ts:
+    srv.wait(t); srv.release(t)
+srv.close(); psf.close(); mix.close()
+print("done")
+'''
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, GFC_LOG="1", PYTHONPATH=root)
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=240, cwd=root)
+    assert r.returncode == 0 and "done" in r.stdout, r.stderr[-2000:]
+    ev = [json.loads(ln) for ln in r.stderr.splitlines() if ln.startswith("{")]
+    kinds = [e["event"] for e in ev]
+    assert "psf_cache_fill" in kinds and kinds.count("server_submit") == 2, kinds
+    launches = [e for e in ev if e["event"] == "batch_launch"]
+    done = {e["batch"] for e in ev if e["event"] == "batch_complete"}
+    assert launches and sum(e["stamps"] for e in launches) == 10 and all(e["W"] == 64 for e in launches)
+    assert {e["batch"] for e in launches} == done
+    assert all(b["t"] >= a["t"] for a, b in zip(ev, ev[1:]))
