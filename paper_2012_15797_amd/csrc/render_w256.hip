@@ -51,7 +51,8 @@ constexpr int RXS = 82;
 // distinct banks.
 constexpr int TWC = 33;
 constexpr int LDS_F2 = HROWS * TS;  // 133 KB
-static_assert(NWAVE * 8 * CXS <= LDS_F2 && NWAVE * 8 * RXS <= LDS_F2, "the exchange slices alias the half buffer");
+static_assert(NWAVE * 8 * CXS <= LDS_F2, "the column exchange slices lie in the half buffer");
+static_assert(8 * RXS <= 8 * TS && (8 * TS) % 16 == 0, "a row exchange slice lies in its wavefront's rows");
 }  // namespace w256
 
 // Orders a wavefront's LDS accesses across this point (they execute in
@@ -472,7 +473,6 @@ __global__ void __launch_bounds__(w256::BLOCK) render_w256_kernel(RenderArgs pa)
         R[m] = make_float2(fmaf(-T::r, u.y, s.x), fmaf(T::r, u.x, s.y));
       });
     }
-    __syncthreads();  // every row is read: the half buffer is free for the row exchange
     fft<16, +1>(R);   // R[n1] = sum_m R_in[m] exp(2 pi i m n1 / 16)
     static_for<1, 16>([&](auto nn) {
       constexpr int n1 = decltype(nn)::value;
@@ -483,7 +483,10 @@ __global__ void __launch_bounds__(w256::BLOCK) render_w256_kernel(RenderArgs pa)
     // R_0..7[2 r + kk]
     float2 zq[2][8];
     {
-      float2* rxb = s_buf + wv * (8 * RXS) + yl * RXS;  // this row's slot
+      // This wavefront's slice lies in the eight rows of the half that only
+      // it reads (rows 8 wv .. 8 wv + 7, read above): no barrier is needed
+      // before it is reused.
+      float2* rxb = s_buf + wv * (8 * TS) + yl * RXS;  // this row's slot
       static_for<0, 2>([&](auto kk) {
         constexpr int k = decltype(kk)::value;
         static_for<0, 8>([&](auto ii) {
