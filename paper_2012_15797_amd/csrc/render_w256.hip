@@ -22,6 +22,8 @@
 //                  radix-8 stage through the wavefront's LDS slice), add the
 //                  real-space components (step 8) to their 32 pixels and
 //                  store them.
+#include <atomic>
+
 #include "gfc_device.hpp"
 #include "gfc_launch.hpp"
 
@@ -548,23 +550,27 @@ __global__ void __launch_bounds__(w256::BLOCK) render_w256_kernel(RenderArgs pa)
 
 // Workgroups of one instantiation resident at once on the current device
 // (one per CU), queried once per device.
+// (Launches from several host threads may fill an entry at once; they store
+// the same value.)
 template <bool EIG, bool PT>
 static hipError_t w256_resident(int64_t* out) {
   constexpr int kMaxDev = 64;
-  static int64_t cached[kMaxDev] = {};
+  static std::atomic<int64_t> cached[kMaxDev];
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   if (dev < 0 || dev >= kMaxDev) return hipErrorInvalidDevice;
-  if (cached[dev] == 0) {
+  int64_t v = cached[dev].load(std::memory_order_relaxed);
+  if (v == 0) {
     int cus = 0, per = 0;
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, render_w256_kernel<EIG, PT>, w256::BLOCK, 0);
     if (e != hipSuccess) return e;
-    cached[dev] = (int64_t)std::max(per, 1) * std::max(cus, 1);
+    v = (int64_t)std::max(per, 1) * std::max(cus, 1);
+    cached[dev].store(v, std::memory_order_relaxed);
   }
-  *out = cached[dev];
+  *out = v;
   return hipSuccess;
 }
 
