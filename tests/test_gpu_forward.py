@@ -174,6 +174,36 @@ def test_large_workload_full_size_sampled(ctx):
     psf.close(); mix.close()
 
 
+@pytest.mark.parametrize("flags,cd", [(1, None), (0, None), (4, None), (1, (1.3, 0.4, -0.2, 0.7))])
+def test_w256_negligible_block_skip_extremes(ctx, flags, cd):
+    """At 256 x 256 a block of Fourier bins is skipped for a component when a
+    bound from the smallest eigenvalue of the shape matrix puts every
+    exponent in it below -40.  The bound is tightest for wide, elongated
+    galaxies: r_e from 2 to 60 px, |e| up to 0.69 at four orientations, every
+    component forced to Fourier space (the widest are then skipped almost
+    everywhere), the hybrid and linear-ramp routings, and a sheared,
+    anisotropic CD matrix."""
+    cfg = wl.config3(10)
+    rng = np.random.Generator(np.random.PCG64(4040))
+    r_e, e1, e2 = [], [], []
+    for r in (2.0, 8.0, 20.0, 40.0, 60.0):
+        for e, th in ((0.0, 0.0), (0.69, 0.0), (0.69, 0.785), (0.5, 1.571), (0.69, 2.356)):
+            r_e.append(r); e1.append(e * math.cos(2 * th)); e2.append(e * math.sin(2 * th))
+    n = len(r_e)
+    f32 = lambda a: np.asarray(a, np.float32)
+    gal = wl.Galaxies(f32(128.0 + rng.uniform(0, 1, n)), f32(128.0 + rng.uniform(0, 1, n)),
+                      f32(rng.uniform(1.0, 1e3, n)), f32(r_e), f32(e1), f32(e2), np.zeros(n, np.int32),
+                      np.full(n, 256, np.int32))
+    cdv = None if cd is None else np.asarray(cd, np.float32)
+    psf, mix = lib_objects(ctx, cfg)
+    gpu = render_gpu(ctx, psf, mix, gal, 256, flags=flags, cd=cdv)
+    idx = list(range(n))
+    ref = oracle_stamps(cfg, gal, idx, flags=flags, cd=None if cdv is None else cdv.astype(np.float64))
+    errs = peak_errors(gpu, ref, idx)
+    assert errs.max() <= TOL_PEAK, (errs.max(), int(errs.argmax()))
+    psf.close(); mix.close()
+
+
 def test_w256_persistent_rounds_tables_and_invalid():
     """At 256 x 256 a workgroup takes stamps in turn and loads the next
     stamp's inputs while it renders the current one.  600 galaxies (two to
