@@ -55,7 +55,7 @@ FP32_FMA_NONPACKED_TFLOPS = CU * SIMD_PER_CU * LANES_PER_SIMD * 2 * CLOCK_HZ / 1
 FP32_PUBLISHED_TFLOPS = 157.3   # counts packed FP32 FMAs, which this build does not use
 HBM_GBPS = 8000.0
 TOL_PEAK = 1e-5                 # forward parity bar: max |gpu - oracle| <= TOL_PEAK x peak
-CPU_SHARE = 16                  # CPUs a one-GPU machine gives this process
+CPU_SHARE = 16                  # host CPUs that go with one GPU
 
 KQ = -2.0 * math.pi**2 * math.log2(math.e)
 
@@ -364,7 +364,7 @@ def cpu_leg(n_metric, sample, workers, other, serve_seconds=0.0):
                host_cpu_count=host_cpus, cpus_available=share,
                sample=f"{sample} seeded stamps of the 100k workload, FP64 oracle, {workers} single-threaded "
                       f"processes (host os.cpu_count() {host_cpus}, {share} CPUs in this process's affinity, "
-                      f"of which a one-GPU box grants {CPU_SHARE}); {cpu_s:.1f} CPU-s, the slowest process "
+                      f"of which one GPU's share is {CPU_SHARE}); {cpu_s:.1f} CPU-s, the slowest process "
                       f"{span:.2f} s in the oracle (value = sample / that), {wall:.2f} s wall with start-up")
     refs = {}
     serve = {f"serving_{label or 'full_'}": [label, rate, secs, restricted]

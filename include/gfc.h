@@ -195,10 +195,12 @@ typedef struct {
 /* Steps 3-8 for n galaxies into stamps of size W, asynchronously on
  * hip_stream.  out: device, n*W*W float32 [n][W][W].  Galaxies with invalid
  * parameters get an all-NaN stamp and increment the invalid counter; the
- * call itself does not synchronise.  n == 0 is a no-op.  W = 256 takes a
- * stream-ordered device slab of 264 KiB per resident workgroup (as many as
- * the device keeps resident, two per CU on MI355X, at most n) inside the
- * call. */
+ * call itself does not synchronise.  n == 0 is a no-op.  Apart from the
+ * PSF-FT cache fill of the first call for a PSF and W (gfc_psf_prepare
+ * makes it beforehand), no device memory is allocated inside the call at
+ * any W: the half spectrum stays on the chip (at W = 256 one workgroup per
+ * CU renders a stamp at a time).  The Sersic and composite renders below
+ * allocate their per-galaxy tables. */
 gfc_status gfc_render_stamps(gfc_ctx* ctx, gfc_psf* psf, const gfc_mix* mix,
                              const gfc_galaxies* gal, int64_t n, int W, unsigned flags,
                              float* out, void* hip_stream);

@@ -189,9 +189,10 @@ gfc_status gfc_ctx_create(int hip_device, gfc_ctx** out) {
     delete ctx;
     return fail(GFC_ENOMEM, "invalid-counter allocation failed");
   }
-  // Stream-ordered scratch (the W = 256 slab, the adjoint workspace, serving
-  // batches) comes from the device's default memory pool; keep freed blocks
-  // cached in it instead of returning them to the driver at every
+  // Stream-ordered scratch (the W = 256 adjoint's slab, the adjoint
+  // workspace, per-galaxy mixture tables, serving fallbacks) comes from the
+  // device's default memory pool; keep freed blocks
+  // cached in it instead of returning them to the HIP runtime at every
   // synchronisation, so repeated calls do not pay for fresh allocations.
   hipMemPool_t pool = nullptr;
   if (hipDeviceGetDefaultMemPool(&pool, hip_device) == hipSuccess && pool) {
