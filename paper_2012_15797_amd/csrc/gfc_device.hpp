@@ -95,13 +95,16 @@ __device__ __forceinline__ Galaxy make_galaxy(const RenderArgs& p, const GalaxyI
   G.y0 = in.y;
   G.flux = in.flux;
   const float re = in.re, e1 = in.e1, e2 = in.e2;
-  G.table = in.table;
+  // The table follows from mix_id alone (an index out of range takes table
+  // 0 and makes the galaxy invalid), so its reads need not wait for the
+  // other parameters.
+  const bool table_ok = in.table >= 0 && in.table < p.n_tables;
+  G.table = table_ok ? in.table : 0;
+  G.K = p.K[G.table];
   const float esq = e1 * e1 + e2 * e2;
   G.ok = finitef(G.x0) && finitef(G.y0) && finitef(G.flux) && finitef(re) && finitef(e1) &&
          finitef(e2) && re > 0.f && esq < 1.f && fabsf(G.x0) <= 8388608.f &&
-         fabsf(G.y0) <= 8388608.f && G.table >= 0 && G.table < p.n_tables;
-  if (!G.ok) G.table = 0;
-  G.K = p.K[G.table];
+         fabsf(G.y0) <= 8388608.f && table_ok;
   // An invalid galaxy renders as NaN everywhere: a NaN flux propagates
   // through every product of the Fourier and real-space paths.
   if (!G.ok) G.flux = __builtin_nanf("");
@@ -148,6 +151,18 @@ __device__ __forceinline__ float shape_min_eig(const Galaxy& G) {
   const double h = 0.5 * (a - d);
   const double lam = 0.5 * (a + d) - sqrt(h * h + b * b);
   return lam > 0.0 ? (float)(0.999 * lam) : 0.f;
+}
+
+// A kernel's first argument A, read through a pointer that is renewed
+// opaquely at each call: its fields are reloaded through the scalar cache
+// there instead of being held in registers from the kernel's start (inside
+// a persistent loop, or late in a long kernel).
+template <typename A>
+__device__ __forceinline__ const A& kernel_args_renewed() {
+  typedef const __attribute__((address_space(4))) A* KArgs;
+  KArgs pk = (KArgs)__builtin_amdgcn_kernarg_segment_ptr();
+  asm volatile("" : "+s"(pk));
+  return *(const A*)pk;
 }
 
 __device__ __forceinline__ float uniform_f(float v) {

@@ -62,6 +62,37 @@ __device__ __forceinline__ float seg_sum(float v, float* s_x2) {
   return v;
 }
 
+// Five such sums with one meeting in LDS for W = 128.
+template <int W>
+__device__ __forceinline__ void seg_sum5(float& a, float& b, float& c, float& d, float& e, float* s_x10) {
+  constexpr int LIM = W < 64 ? W : 64;
+#pragma unroll
+  for (int o = 1; o < LIM; o <<= 1) {
+    a += __shfl_xor(a, o);
+    b += __shfl_xor(b, o);
+    c += __shfl_xor(c, o);
+    d += __shfl_xor(d, o);
+    e += __shfl_xor(e, o);
+  }
+  if constexpr (W == 128) {
+    const int wv = (threadIdx.x >> 6) & 1;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+      s_x10[wv] = a;
+      s_x10[2 + wv] = b;
+      s_x10[4 + wv] = c;
+      s_x10[6 + wv] = d;
+      s_x10[8 + wv] = e;
+    }
+    __syncthreads();
+    a = s_x10[0] + s_x10[1];
+    b = s_x10[2] + s_x10[3];
+    c = s_x10[4] + s_x10[5];
+    d = s_x10[6] + s_x10[7];
+    e = s_x10[8] + s_x10[9];
+  }
+}
+
 template <int W>
 __global__ void __launch_bounds__(BwdCfg<W>::BLOCK) __attribute__((amdgpu_waves_per_eu(BwdCfg<W>::WPE)))
 render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __restrict__ grad_params,
@@ -75,10 +106,11 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
   __shared__ float2 s_nyq[C::SPB][W];
   __shared__ float s_racc[C::SPB][kKmax][6];
   __shared__ float4 s_cmp[C::SPB][kKmax];  // per component: v, w A, w A v (zero when unused)
-  __shared__ float s_x2[2];
+  __shared__ float s_x2[10];
 
-  const int l = threadIdx.x % W;
-  const int slot = threadIdx.x / W;
+  // with one stamp per workgroup the stamp index is uniform (scalar)
+  const int l = C::SPB == 1 ? (int)threadIdx.x : (int)threadIdx.x % W;
+  const int slot = C::SPB == 1 ? 0 : (int)threadIdx.x / W;
   const int64_t stamp = (int64_t)blockIdx.x * C::SPB + slot;
   const bool live = stamp < p.n;
   const int64_t gidx = live ? stamp : p.n - 1;
@@ -94,18 +126,28 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
   // per-component constants of the Fourier sums, computed once per stamp:
   // v, w A, w A v and w (w = 0 past the table's K).  A component with A = 0
   // still needs its sums: dL/dA does not depend on A.
-  if (l < kKmax) {
-    const float v = var[l];
-    const bool in = l < G.K;
-    const float w = in ? route_weight<W>(v * trB, p.flags) : 0.f;
-    const float wa = w * (in ? amp[l] : 0.f);
-    s_cmp[slot][l] = make_float4(v, wa, wa * v, w);
+  bool real_share = false;  // lane k < K of each wavefront: component k has a real-space share
+  {
+    const int k = l & 63;
+    if (k < kKmax) {
+      const float v = var[k];
+      const bool in = k < G.K;
+      const float w = in ? route_weight<W>(v * trB, p.flags) : 0.f;
+      const float wa = w * (in ? amp[k] : 0.f);
+      if (l < kKmax) s_cmp[slot][l] = make_float4(v, wa, wa * v, w);
+      real_share = in && w < 1.f;
+    }
   }
 
-  // routing: components with a real-space share (whatever their amplitude)
+  // routing: components with a real-space share (whatever their amplitude);
+  // with one stamp per workgroup, from the lanes' weights
   unsigned rmask = 0;
-  for (int k = 0; k < kloop; ++k) {
-    if (k < G.K && route_weight<W>(var[k] * trB, p.flags) < 1.f) rmask |= 1u << k;
+  if constexpr (C::SPB == 1) {
+    rmask = (unsigned)__ballot(real_share) & ((1u << kKmax) - 1u);
+  } else {
+    for (int k = 0; k < kloop; ++k) {
+      if (k < G.K && route_weight<W>(var[k] * trB, p.flags) < 1.f) rmask |= 1u << k;
+    }
   }
 
   // ------------------------------------------------------------ load + real space
@@ -161,11 +203,7 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
         float axy = fmaf(be, m2, al * m1);
         float axx = fmaf(be, axy, al * ax);
         a0 = seg_sum<W>(a0, s_x2);
-        ax = seg_sum<W>(ax, s_x2);
-        ay = seg_sum<W>(ay, s_x2);
-        axx = seg_sum<W>(axx, s_x2);
-        axy = seg_sum<W>(axy, s_x2);
-        ayy = seg_sum<W>(ayy, s_x2);
+        seg_sum5<W>(ax, ay, axx, axy, ayy, s_x2);
         if (l == 0) {
           s_racc[slot][k][0] += a0;
           s_racc[slot][k][1] += ax;
@@ -198,15 +236,15 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
       const float2 e2 = cadd(a, b);
       const float2 o2 = rot90<-1>(csub(a, b));      // -i (a - b)
       // t2 = exp(-2 pi i k / W) o2 = r u (TwFactor): e2 +- t2 as FMAs
-      using T = TwFactor<-1, W, k>;
-      const float2 u = T::unit(o2);
+      using TF = TwFactor<-1, W, k>;
+      const float2 u = TF::unit(o2);
       if constexpr (k == 0) {
         // Gr2[0] and Gr2[W/2] are real: stored packed as (Gr2[0], Gr2[W/2]) in
         // column 0, which the column DFT transforms as one complex column
         gr[y * (M + 1)] = make_float2(e2.x + u.x, e2.x - u.x);
       } else {
-        gr[y * (M + 1) + k] = make_float2(fmaf(T::r, u.x, e2.x), fmaf(T::r, u.y, e2.y));
-        if constexpr (2 * k != M) gr[y * (M + 1) + (M - k)] = make_float2(fmaf(-T::r, u.x, e2.x), fmaf(T::r, u.y, -e2.y));
+        gr[y * (M + 1) + k] = make_float2(fmaf(TF::r, u.x, e2.x), fmaf(TF::r, u.y, e2.y));
+        if constexpr (2 * k != M) gr[y * (M + 1) + (M - k)] = make_float2(fmaf(-TF::r, u.x, e2.x), fmaf(TF::r, u.y, -e2.y));
       }
     });
   }
@@ -331,11 +369,12 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
 
   // ------------------------------------------------------------ component loop
   float ax = 0.f, ay = 0.f, a11 = 0.f, a12 = 0.f, a22 = 0.f;
-  // per-lane p_k partials [kKmax][W + 1] in the g tile, which the column DFT
-  // has finished reading.  Rows are W + 1 floats apart, so when lane k sums
-  // row k below, the 16 lanes read 16 different banks (at a row stride of W
-  // they all read one bank: about 240 conflict cycles per wavefront at 64).
-  constexpr int PKS = W + 1;
+  // per-lane p_k partials [kKmax][PKS] in the g tile, which the column DFT
+  // has finished reading.  The row stride W + LPK makes the reduction below
+  // free of bank conflicts.
+  constexpr int LPK = W / kKmax;  // lanes per component in that reduction
+  static_assert(LPK >= 1 && W % kKmax == 0, "components share the stamp's lanes evenly");
+  constexpr int PKS = W + LPK;
   float* s_pk = &s_tile[slot][0];
   static_assert(kKmax * PKS <= C::TN, "p_k partials fit in the tile");
   for (int k = 0; k < kKmax; ++k) s_pk[k * PKS + l] = 0.f;
@@ -351,10 +390,19 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
       S[j] = 0.f;
       S1[j] = 0.f;
     });
+    // The next component's constants and partial are read one iteration
+    // ahead, so that the LDS latency falls behind this component's work.
+    float4 cpn = s_cmp[slot][0];
+    float pkn = s_pk[l];
     for (int k = 0; k < kloop; ++k) {
       // p_k is needed when w_k > 0 (amplitude and ramp terms); w_k = 0 means n_k <= 3,
       // where the ramp slope vanishes too
-      const float4 cp = s_cmp[slot][k];
+      const float4 cp = cpn;
+      const float pk_before = pkn;
+      if (k + 1 < kloop) {
+        cpn = s_cmp[slot][k + 1];
+        pkn = s_pk[(k + 1) * PKS + l];
+      }
       const float v = cp.x, wa = cp.y, wav = cp.z;
       if (cp.w == 0.f) continue;
       float pk = 0.f;
@@ -365,7 +413,7 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
         S1[j] = fmaf(wav, e, S1[j]);
         pk = fmaf(ure[b0 + j], e, pk);
       });
-      s_pk[k * PKS + l] += pk;
+      s_pk[k * PKS + l] = pk_before + pk;
     }
     static_for<0, nb>([&](auto jj) {
       constexpr int j = decltype(jj)::value;
@@ -383,17 +431,19 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
     // the accumulation (and keep this block's sums alive) past later blocks.
     asm volatile("" : "+v"(ax), "+v"(ay), "+v"(a11), "+v"(a12), "+v"(a22));
   });
-  ax = seg_sum<W>(ax, s_x2);
-  ay = seg_sum<W>(ay, s_x2);
-  a11 = seg_sum<W>(a11, s_x2);
-  a12 = seg_sum<W>(a12, s_x2);
-  a22 = seg_sum<W>(a22, s_x2);
+  seg_sum5<W>(ax, ay, a11, a12, a22, s_x2);
   __syncthreads();
-  // p_k = sum over the stamp's lanes, fixed order; lane k of the stamp sums row k
-  if (l < kKmax) {
+  // p_k = sum over the stamp's W partials, fixed order: LPK lanes per
+  // component, lane i taking the entries i, i + LPK, ..., then a butterfly
+  // over the LPK lanes.
+  {
+    const int k = l / LPK, i = l % LPK;
     float acc = 0.f;
-    for (int i = 0; i < W; ++i) acc += s_pk[l * PKS + i];
-    s_pk[l * PKS] = acc;
+#pragma unroll
+    for (int e = 0; e < W / LPK; ++e) acc += s_pk[k * PKS + i + e * LPK];
+#pragma unroll
+    for (int o = 1; o < LPK; o <<= 1) acc += __shfl_xor(acc, o);
+    if (i == 0) s_pk[k * PKS] = acc;
   }
   __syncthreads();
 
@@ -401,13 +451,19 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
   // lane k of the stamp takes component k; the terms are summed over 16 lanes
   // and lane 0 finishes B -> (log r_e, e1, e2)
   {
-    Galaxy Gc = load_galaxy<W>(p, gidx);  // reloaded: keeps G's registers free in the loops above
+    // The galaxy is reloaded here, through renewed argument and stamp
+    // values, so that neither it nor its addresses hold registers through
+    // the loops above.
+    const RenderArgs& pc = kernel_args_renewed<RenderArgs>();
+    int64_t gi = gidx;
+    if constexpr (C::SPB == 1) asm volatile("" : "+s"(gi));
+    Galaxy Gc = load_galaxy<W>(pc, gi);
     if constexpr (C::SPB == 1) make_uniform(Gc);
     CompTerms t = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (live && l < kKmax)
-      t = bwd_component_terms<W>(p, Gc, l, rmask, s_pk, PKS, &s_racc[slot][0][0], amp_part + gidx * kKmax);
+      t = bwd_component_terms<W>(pc, Gc, l, rmask, s_pk, PKS, &s_racc[slot][0][0], amp_part + gi * kKmax);
     t = sum16(t);
-    if (l == 0 && live) bwd_chain_finish<W>(p, Gc, gidx, ax, ay, a11, a12, a22, t, grad_params);
+    if (l == 0 && live) bwd_chain_finish<W>(pc, Gc, gi, ax, ay, a11, a12, a22, t, grad_params);
   }
 }
 

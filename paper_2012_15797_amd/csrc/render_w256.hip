@@ -74,17 +74,6 @@ __device__ __forceinline__ float2 ld2(GlobalF2 a, int i) {
   return make_float2(v.x, v.y);
 }
 
-// The kernel's (single) argument, read through a pointer that is renewed
-// opaquely at each call: inside a persistent loop its fields are reloaded
-// through the scalar cache instead of being held in scalar registers.
-template <typename A>
-__device__ __forceinline__ const A& kernel_args_renewed() {
-  typedef const __attribute__((address_space(4))) A* KArgs;
-  KArgs pk = (KArgs)__builtin_amdgcn_kernarg_segment_ptr();
-  asm volatile("" : "+s"(pk));
-  return *(const A*)pk;
-}
-
 // Inputs of stamp g that the kernel reads per stamp, as 32-bit words:
 // x, y, flux, r_e, e1, e2, mixture id, PSF id (PT), PSF position (EIG).
 constexpr int kInWords = 10;
