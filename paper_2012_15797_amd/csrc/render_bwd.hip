@@ -38,6 +38,10 @@ struct BwdCfg {
   static constexpr int SPB = BLOCK / W;
   static constexpr int TS = W + 2;            // floats per row of the g tile / float2 per row of Gr is W/2+1
   static constexpr int TN = W * (W + 2);      // floats per stamp
+  // Floats from one stamp's tile to the next.  At W = 16 two stamps share
+  // each 32-lane half of a wavefront, whose 4-byte LDS accesses are served
+  // together: a stride of 16 (mod 32) puts the two stamps in different banks.
+  static constexpr int TNP = W < 32 ? TN + 16 : TN;
   static constexpr int CH = W <= 64 ? W : 32; // rows per load chunk
   static constexpr int NP = M + 3;            // evaluation points per lane
   static constexpr int PB = M <= 16 ? NP : 8;   // points per block of the component loop
@@ -101,7 +105,7 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
   constexpr int M = C::M;
   constexpr int NP = C::NP;
   constexpr int TS = C::TS;
-  __shared__ float s_tile[C::SPB][C::TN];
+  __shared__ float s_tile[C::SPB][C::TNP];
   __shared__ float2 s_py[C::SPB][W + 2];
   __shared__ float2 s_nyq[C::SPB][W];
   __shared__ float s_racc[C::SPB][kKmax][6];
