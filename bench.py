@@ -67,11 +67,13 @@ def log(msg):
 # ---------------------------------------------------------------- work accounting
 def routing_counts(gal, var, W):
     """K_F (components with Fourier weight > 0) and K_R (weight < 1) per galaxy,
-    from the closed-form pixel covariance trace: tr C_i = v_i r_e^2 (2 + 2 e^2)/(1 + e)^2."""
+    from the closed-form pixel covariance trace: tr C_i = v_i r_e^2 (2 + 2 e^2)/(1 + e)^2.
+    var: the components' variances [K], or per galaxy [n][K]."""
     r = gal.r_e.astype(np.float64)
     e = np.hypot(gal.e1.astype(np.float64), gal.e2.astype(np.float64))
     tr = r * r * (2.0 + 2.0 * e * e) / (1.0 + e) ** 2
-    n = (W / 2.0) / np.sqrt(var[None, :] * tr[:, None])
+    var = np.asarray(var, np.float64)
+    n = (W / 2.0) / np.sqrt((var[None, :] if var.ndim == 1 else var) * tr[:, None])
     kf = (n > 3.0).sum(axis=1)
     kr = (n < 4.0).sum(axis=1)
     return kf, kr
@@ -114,6 +116,27 @@ def workload_flops(gal, mix, W, adjoint=False):
         kf, kr = routing_counts(gal.subset(sel), np.asarray(mix.var[t, :k], np.float64), W)
         total += float(f(W, kf, kr).sum())
     return total
+
+
+def pergal_flops(gal, var, W):
+    """Algorithmic FLOPs of one forward launch whose galaxy i has its own
+    component variances var[i] (the interpolated Sersic and the bulge + disk
+    mixtures)."""
+    kf, kr = routing_counts(gal, var, W)
+    return float(algorithmic_flops_per_stamp(W, kf, kr).sum())
+
+
+def eigen_psf_flops(W, J):
+    """FLOPs per stamp of forming a varying PSF's spectrum from J component
+    spectra (a real weight times a complex value, accumulated: 4 per
+    component and bin of the half spectrum and Nyquist column)."""
+    return 4.0 * J * (W * (W // 2 + 1) + W)
+
+
+def lanczos_flops(W):
+    """FLOPs per stamp of the separable six-tap Lanczos-3 shift (an FMA per
+    tap along x, then along y)."""
+    return 24.0 * W * W
 
 
 def flops_roofline(flops, ms):
@@ -911,7 +934,9 @@ def size_throughput(gfc, ctx, dev, refs, reps=5):
     rows = lambda ii: out[torch.as_tensor(ii, device=dev)].cpu().numpy().astype(np.float64)
     ms = timed(lambda: gfc.gfc_render_stamps(ctx, psf, mix, *args, 64, out=out, flags=gfc.GFC_SHIFT_LANCZOS3),
                reps * 4)
-    res["lanczos3-dev8-64x64-100k"] = line(len(g), ms, parity=rows_parity("lanczos", rows))
+    res["lanczos3-dev8-64x64-100k"] = line(
+        len(g), ms, parity=rows_parity("lanczos", rows),
+        roofline=flops_roofline(workload_flops(g, cfg["mix"], 64) + len(g) * lanczos_flops(64), ms))
     psf.close()
     mix.close()
 
@@ -923,7 +948,12 @@ def size_throughput(gfc, ctx, dev, refs, reps=5):
     args = [d(a) for a in (g.x, g.y, g.flux, g.r_e, g.e1, g.e2)]
     sn = d(cfg["sersic_n"])
     ms = timed(lambda: gfc.gfc_render_stamps_sersic(ctx, psf, fam, *args, sn, 64, out=out), reps * 4)
-    res["sersic8-64x64-100k"] = line(len(g), ms, parity=rows_parity("sersic", rows))
+    fam_t = cfg["family"]
+    n_of = np.asarray(cfg["sersic_n"], np.float64)
+    var_g = np.stack([np.interp(n_of, fam_t["n_grid"].astype(np.float64), fam_t["var"][:, k].astype(np.float64))
+                      for k in range(fam_t["var"].shape[1])], axis=1)  # piecewise-linear in n, per component
+    res["sersic8-64x64-100k"] = line(len(g), ms, parity=rows_parity("sersic", rows),
+                                     roofline=flops_roofline(pergal_flops(g, var_g, 64), ms))
     psf.close()
     fam.close()
     cfg = wl.config_composite()
@@ -933,7 +963,12 @@ def size_throughput(gfc, ctx, dev, refs, reps=5):
     args = [d(a) for a in (g.x, g.y, g.flux, g.r_e, g.e1, g.e2)]
     fr, rh = d(cfg["bulge_frac"]), d(cfg["bulge_rho"])
     ms = timed(lambda: gfc.gfc_render_stamps_composite(ctx, psf, mix, 0, 1, *args, fr, rh, 64, out=out), reps * 4)
-    res["composite14-64x64-100k"] = line(len(g), ms, parity=rows_parity("composite", rows))
+    _, var_d = cfg["mix"].table(0)
+    _, var_b = cfg["mix"].table(1)
+    rho2 = np.asarray(cfg["bulge_rho"], np.float64) ** 2
+    var_g = np.concatenate([np.broadcast_to(var_d, (len(g), len(var_d))), rho2[:, None] * var_b[None, :]], axis=1)
+    res["composite14-64x64-100k"] = line(len(g), ms, parity=rows_parity("composite", rows),
+                                         roofline=flops_roofline(pergal_flops(g, var_g, 64), ms))
     psf.close()
     mix.close()
 
@@ -945,7 +980,10 @@ def size_throughput(gfc, ctx, dev, refs, reps=5):
     args = [d(a) for a in (g.x, g.y, g.flux, g.r_e, g.e1, g.e2)]
     px, py = d(cfg["psf_x"]), d(cfg["psf_y"])
     ms = timed(lambda: gfc.gfc_render_stamps(ctx, psf, mix, *args, 64, out=out, psf_x=px, psf_y=py), reps * 4)
-    res["eigenpsf6-dev8-64x64-100k"] = line(len(g), ms, parity=rows_parity("eigen", rows))
+    J = len(e["comps"])
+    res["eigenpsf6-dev8-64x64-100k"] = line(
+        len(g), ms, parity=rows_parity("eigen", rows),
+        roofline=flops_roofline(workload_flops(g, cfg["mix"], 64) + len(g) * eigen_psf_flops(64, J), ms))
     del out
     psf.close()
     mix.close()
