@@ -18,15 +18,18 @@ Order of a run:
      the reference samples that gate every other reported number.
   2. Rate probes of the device (FMA, v_exp_f32, HBM write and copy): the
      measured roofline denominators.
-  3. Settle steps (default 45): a fresh GPU under this full load runs a few
-     launches fast, is then throttled by its power management (about 0.75
-     ms per launch instead of 0.52) and reaches steady clocks after about 40
-     launches.  These untimed steps carry it through that transient, then W
-     warm-up steps, then K timed steps (HIP events on the launch stream).
+  3. Settle steps (at least 45 and 50 ms of device time): a GPU that was
+     idle runs a few launches of this full load fast, is then throttled by
+     its power management (about 0.75 ms per launch instead of 0.52) and
+     reaches steady clocks after about 25 ms.  These untimed steps carry it
+     through that transient, then W warm-up steps, then K timed steps (HIP
+     events on the launch stream).
   4. Parity of the timed output, the plain per-request launches, serving,
      and the other workloads, each with a parity record from its own launch.
+     Each other workload is timed after untimed launches of its own by the
+     same rule.
 
-    python bench.py [--gpus 1] [--steps 100] [--warmup 30] [--settle 45]
+    python bench.py [--gpus 1] [--steps 100] [--warmup 30] [--settle 45] [--settle-ms 50]
 """
 
 from __future__ import annotations
@@ -137,6 +140,28 @@ def lanczos_flops(W):
     """FLOPs per stamp of the separable six-tap Lanczos-3 shift (an FMA per
     tap along x, then along y)."""
     return 24.0 * W * W
+
+
+def settle_device(fn, min_launches, min_ms, batch=8, max_launches=200_000):
+    """Runs fn untimed until at least min_launches launches and min_ms of
+    device time (HIP events over batches of launches) have passed; returns
+    the number of launches.  A device that was idle goes through a
+    power-management transient (a fast start, a throttled stretch, then
+    steady clocks) that takes tens of milliseconds of full load, whatever
+    the length of one launch."""
+    import torch
+
+    n, t = 0, 0.0
+    while (n < min_launches or t < min_ms) and n < max_launches:
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(batch):
+            fn()
+        b.record()
+        b.synchronize()
+        t += a.elapsed_time(b)
+        n += batch
+    return n
 
 
 def flops_roofline(flops, ms):
@@ -482,9 +507,11 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--settle", type=int, default=45,
-                    help="untimed steps before the warm-up that carry the device through its power-management "
-                         "transient (a fast start, a throttled stretch, then steady clocks after about 40 full-load "
-                         "launches); reported as settle_steps")
+                    help="least number of untimed steps before the warm-up that carry the device through its "
+                         "power-management transient (a fast start, a throttled stretch, then steady clocks after "
+                         "about 25 ms of full load); the count run is reported as settle_steps")
+    ap.add_argument("--settle-ms", type=float, default=50.0,
+                    help="least device time of those settle steps (and of each other case's untimed launches)")
     ap.add_argument("--n", type=int, default=100_000)
     ap.add_argument("--cpu-sample", type=int, default=20000)
     ap.add_argument("--cpu-workers", type=int, default=0)
@@ -501,6 +528,8 @@ def main():
                     help="only launch every kernel instantiation a few times (for rocprofv3) and print "
                          "their launch times")
     ap.add_argument("--profile-reps", type=int, default=3)
+    ap.add_argument("--profile-settle", type=int, default=0,
+                    help="untimed launches of each --profile-set case before its timed ones")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -515,7 +544,7 @@ def main():
         import paper_2012_15797_amd as gfc
 
         dev = torch.device("cuda", 0)
-        res = profile_set(gfc, gfc.Context.default(0), dev, args.profile_reps)
+        res = profile_set(gfc, gfc.Context.default(0), dev, args.profile_reps, args.profile_settle)
         if args.copy_calibration:
             a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
             b = torch.empty_like(a)
@@ -571,12 +600,11 @@ def main():
     # of 0.52) and recovers over about 40 launches.  These untimed steps carry
     # the device through that transient, so the timed steps measure the steady
     # state at any --warmup.
-    for _ in range(args.settle):
-        step()
+    settle_steps = settle_device(step, args.settle, args.settle_ms)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    log(f"settle ({args.settle} steps) and warmup ({args.warmup} steps) done")
+    log(f"settle ({settle_steps} steps) and warmup ({args.warmup} steps) done")
 
     stream = torch.cuda.current_stream(dev)     # the stream the library launches on
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -648,7 +676,7 @@ def main():
 
     other = None
     if not args.no_other:
-        other = size_throughput(gfc, ctx, dev, refs)
+        other = size_throughput(gfc, ctx, dev, refs, settle=args.settle, settle_ms=args.settle_ms)
         log(f"other workloads: {json.dumps(other)}")
 
     if args.copy_calibration:
@@ -662,7 +690,7 @@ def main():
 
     rec = dict(
         metric=METRIC, value=round(value, 1), unit="stamps/s", n_gpus=1, steps=args.steps,
-        warmup=args.warmup, settle_steps=args.settle, ms_per_step=round(ms_per_step, 4), higher_is_better=True,
+        warmup=args.warmup, settle_steps=settle_steps, ms_per_step=round(ms_per_step, 4), higher_is_better=True,
         scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
         config=dict(workload="dev8-64x64-moffat-100k", n_stamps=args.n, W=W, K=8,
                     mixture="DEV8 synthetic (Dirichlet amplitudes, variances logspace 1e-4..10 r_e^2)",
@@ -677,9 +705,10 @@ def main():
     print(json.dumps(rec), flush=True)
 
 
-def profile_set(gfc, ctx, dev, reps=3):
+def profile_set(gfc, ctx, dev, reps=3, settle=0):
     """Every kernel instantiation of the library, launched `reps` times after
-    one untimed launch, for rocprofv3 kernel traces and counters: the forward
+    untimed launches (one, or with settle > 0 at least that many and 50 ms of
+    device time), for rocprofv3 kernel traces and counters: the forward
     render at 16, 32, 64, 128 and 256 (the throughput workload's galaxies,
     radii scaled to the stamp; the large workload at 128 and 256), its
     eigen-PSF, Lanczos (fused at 64, separate passes at 128 and 256), Sersic
@@ -692,7 +721,10 @@ def profile_set(gfc, ctx, dev, reps=3):
     res = {}
 
     def run(name, n, fn):
-        fn()
+        if settle > 0:
+            settle_device(fn, settle, 50.0)
+        else:
+            fn()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -855,19 +887,23 @@ def serving_benchmark(gfc, ctx, seconds, refs):
     return out
 
 
-def size_throughput(gfc, ctx, dev, refs, reps=5):
+def size_throughput(gfc, ctx, dev, refs, reps=5, settle=45, settle_ms=50.0):
     """Forward stamps/s per stamp size on the mixed-size and large-galaxy
     workloads (one launch per size bin), the 64x64 workload with Lanczos
     shifting, general Sersic, composites and the eigen-PSF, and the adjoint
     on the differentiation workload.  Every line carries the parity of a
-    seeded sample of its own last launch against the CPU leg's oracle."""
+    seeded sample of its own last launch against the CPU leg's oracle.
+    Each case is timed after untimed launches of its own (at least `settle`
+    launches and `settle_ms` of device time): the host work between cases
+    idles the device, and the first tens of milliseconds of load after that
+    run through the power-management transient the metric's settle steps
+    skip."""
     import torch
 
     d = lambda a: torch.as_tensor(a).to(dev)
 
     def timed(fn, n_reps):
-        for _ in range(3):
-            fn()
+        settle_device(fn, max(3, settle), settle_ms)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
