@@ -117,8 +117,11 @@ __device__ __forceinline__ Galaxy make_galaxy(const RenderArgs& p, const GalaxyI
   G.fy = G.ok ? G.y0 - fyf : 0.f;
   G.nx = G.ok ? ((int)(fxf - (float)W * floorf(fxf * (1.f / W)))) & (W - 1) : 0;
   G.ny = G.ok ? ((int)(fyf - (float)W * floorf(fyf * (1.f / W)))) & (W - 1) : 0;
-  const float e = sqrtf(esq);
-  const float s = (re * re) / ((1.f + e) * (1.f + e));
+  // Hardware square root and reciprocal (about 1 ulp each): the covariance
+  // needs no correctly rounded operations, and these are a few instructions
+  // instead of some thirty.
+  const float e = __builtin_amdgcn_sqrtf(esq);
+  const float s = (re * re) * __builtin_amdgcn_rcpf((1.f + e) * (1.f + e));
   const float c11 = s * (1.f + esq - 2.f * e1);
   const float c12 = s * (2.f * e2);
   const float c22 = s * (1.f + esq + 2.f * e1);

@@ -511,7 +511,7 @@ render_small_kernel(RenderArgs p) {
           // the conditional mean so that no large terms cancel near the peak:
           // with dx = x + dx0 the exponent is k - u^2, u = g (x + m).
           const float rsyy = __builtin_amdgcn_rcpf(syy);
-          const float g = sqrtf(-kHalfLog2e * syy * rdet);
+          const float g = __builtin_amdgcn_sqrtf(-kHalfLog2e * syy * rdet);
           const float k0 = kHalfLog2e * dy * dy * rsyy;
           const float gm = g * fmaf(-sxy * rsyy, dy, dx0);
           static_for<0, W / 2>([&](auto xx) {
@@ -610,7 +610,7 @@ render_small_kernel(RenderArgs p) {
           // (W/2)^2 / syy there).  With dy = dyq + r the exponent is
           // k - u^2, u = g (r + m): two FMAs with an immediate r.
           const float rsxx = __builtin_amdgcn_rcpf(sxx);
-          const float g = sqrtf(-kHalfLog2e * sxx * rdet);
+          const float g = __builtin_amdgcn_sqrtf(-kHalfLog2e * sxx * rdet);
           const float k0 = kHalfLog2e * dx * dx * rsxx;
           const float dyq = (float)(q * C::HR) + dyc;
           const float gm = g * fmaf(-sxy * rsxx, dx, dyq);

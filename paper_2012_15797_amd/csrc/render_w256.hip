@@ -268,7 +268,7 @@ __global__ void __launch_bounds__(w256::BLOCK) render_w256_kernel(RenderArgs pa)
         const float det = fmaf(sxx, syy, -(sxy * sxy));
         const float rsyy = __builtin_amdgcn_rcpf(syy);
         s_rc[k] = make_float4((1.f - w) * A * G.flux * pg[5] * kInv2Pi * __builtin_amdgcn_rsqf(det),
-                              sqrtf(-kHalfLog2e * syy * __builtin_amdgcn_rcpf(det)), sxy * rsyy,
+                              __builtin_amdgcn_sqrtf(-kHalfLog2e * syy * __builtin_amdgcn_rcpf(det)), sxy * rsyy,
                               kHalfLog2e * rsyy);
       }
     }
