@@ -44,7 +44,8 @@ __device__ inline CompTerms bwd_component_terms(const RenderArgs& p, const Galax
     const float sxy = fmaf(v, G.b12, p.pg[3]);
     const float syy = fmaf(v, G.b22, p.pg[4]);
     const float det = fmaf(sxx, syy, -(sxy * sxy));
-    const float ixx = syy / det, ixy = -sxy / det, iyy = sxx / det;
+    const float rdet = __builtin_amdgcn_rcpf(det);  // det > 0: a covariance convolved with the PSF's
+    const float ixx = syy * rdet, ixy = -sxy * rdet, iyy = sxx * rdet;
     const float rk = (1.f - w) * F * A * pamp;
     c.dx = rk * R[1];
     c.dy = rk * R[2];
@@ -56,7 +57,7 @@ __device__ inline CompTerms bwd_component_terms(const RenderArgs& p, const Galax
   ap[k] = G.ok ? F * (w * pk + (1.f - w) * pamp * g0) : 0.f;
   // smooth routing: dL/dw_k * dw/dn * dn/d(b11 or b22)
   const float dLdw = F * A * (pk - pamp * g0);
-  const float dn = -0.5f * n / trB;
+  const float dn = -0.5f * n * __builtin_amdgcn_rcpf(trB);
   const float t = route_slope<W>(n, p.flags) * dLdw * dn;
   c.L11 += t;
   c.L22 += t;
@@ -104,12 +105,15 @@ __device__ inline void bwd_chain_finish(const RenderArgs& p, const Galaxy& G, in
   // C0 = s [[1 + e^2 - 2 e1, 2 e2], [2 e2, 1 + e^2 + 2 e1]], s = r_e^2 / (1 + e)^2
   const float re = p.r_e[gidx], e1 = p.e1[gidx], e2 = p.e2[gidx];
   const float esq = e1 * e1 + e2 * e2, e = sqrtf(esq);
-  const float s = re * re / ((1.f + e) * (1.f + e));
+  const float r1e = __builtin_amdgcn_rcpf(1.f + e);
+  const float s = re * re * (r1e * r1e);
   const float c11 = s * (1.f + esq - 2.f * e1), c12 = 2.f * s * e2, c22 = s * (1.f + esq + 2.f * e1);
   const float dlogre = 2.f * (c11g * c11 + c12g * c12 + c22g * c22);
   float de1 = 0.f, de2 = 0.f;
   if (e > 0.f) {
-    const float ds1 = -2.f * s / (1.f + e) * (e1 / e), ds2 = -2.f * s / (1.f + e) * (e2 / e);
+    // e1 / e and e2 / e stay correctly rounded divisions: e may be as small
+    // as the square root of a denormal
+    const float ds1 = -2.f * s * r1e * (e1 / e), ds2 = -2.f * s * r1e * (e2 / e);
     const float a11e = 1.f + esq - 2.f * e1, a22e = 1.f + esq + 2.f * e1;
     de1 = c11g * (ds1 * a11e + s * (2.f * e1 - 2.f)) + c12g * (ds1 * 2.f * e2) +
           c22g * (ds1 * a22e + s * (2.f * e1 + 2.f));

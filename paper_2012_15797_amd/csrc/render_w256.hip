@@ -246,9 +246,9 @@ __global__ void __launch_bounds__(w256::BLOCK) render_w256_kernel(RenderArgs pa)
   float vmax[4];
   static_for<0, 4>([&](auto bb) {
     constexpr int b = decltype(bb)::value;
-    vmax[b] = uniform_f(kSkipLog2 / (lamq * r2[b]));
+    vmax[b] = uniform_f(kSkipLog2 * __builtin_amdgcn_rcpf(lamq * r2[b]));  // rcp(0) = +inf
   });
-  const float vmaxN = uniform_f(kSkipLog2 / (lamq * 0.25f));  // |nu| = 1/2 or |omega| = 1/2
+  const float vmaxN = uniform_f(kSkipLog2 * __builtin_amdgcn_rcpf(lamq * 0.25f));  // |nu| = 1/2 or |omega| = 1/2
   float S[M];
   float SN[3] = {0.f, 0.f, 0.f};
   static_for<0, M>([&](auto mm) { S[decltype(mm)::value] = 0.f; });
