@@ -384,15 +384,27 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
   float* s_pk = &s_tile[slot][0];
   static_assert(kKmax * PKS <= C::TN, "p_k partials fit in the tile");
   for (int k = 0; k < kKmax; ++k) s_pk[k * PKS + l] = 0.f;
+  // The exponent's quadratic form along this lane's column, expanded about
+  // omega = h/W: at omega = c + h/W with a compile-time c it is
+  // e0 + c (e1 + c g2), two FMAs with immediates.
+  const float g2 = kQ * G.b22, g1 = 2.f * kQ * G.b12 * nu;
+  const float e0 = fmaf(hW, fmaf(g2, hW, g1), kQ * G.b11 * nu * nu);
+  const float e1 = fmaf(2.f * g2, hW, g1);
   static_for<0, (NP + C::PB - 1) / C::PB>([&](auto bb) {
     constexpr int b0 = decltype(bb)::value * C::PB;
     constexpr int nb = (NP - b0) < C::PB ? (NP - b0) : C::PB;
     float gq[nb], S[nb], S1[nb];
     static_for<0, nb>([&](auto jj) {
       constexpr int j = decltype(jj)::value;
-      float n_, o_;
-      point(std::integral_constant<int, b0 + j>{}, n_, o_);
-      gq[j] = kQ * fmaf(G.b11 * n_, n_, fmaf(2.f * G.b12 * n_, o_, G.b22 * o_ * o_));
+      constexpr int jp = b0 + j;
+      if constexpr (jp < M && 2 * jp != W / 2) {
+        constexpr float cm = (2 * jp < W / 2) ? (float)(2 * jp) * (1.f / W) : (float)(2 * jp - W) * (1.f / W);
+        gq[j] = fmaf(cm, fmaf(cm, g2, e1), e0);
+      } else {
+        float n_, o_;
+        point(std::integral_constant<int, jp>{}, n_, o_);
+        gq[j] = kQ * fmaf(G.b11 * n_, n_, fmaf(2.f * G.b12 * n_, o_, G.b22 * o_ * o_));
+      }
       S[j] = 0.f;
       S1[j] = 0.f;
     });
