@@ -384,6 +384,7 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
   float* s_pk = &s_tile[slot][0];
   static_assert(kKmax * PKS <= C::TN, "p_k partials fit in the tile");
   for (int k = 0; k < kKmax; ++k) s_pk[k * PKS + l] = 0.f;
+  float m_si = 0.f, m_csi = 0.f, m_r = 0.f, m_cr = 0.f, m_ccr = 0.f;
   // The exponent's quadratic form along this lane's column, expanded about
   // omega = h/W: at omega = c + h/W with a compile-time c it is
   // e0 + c (e1 + c g2), two FMAs with immediates.
@@ -435,20 +436,39 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
     }
     static_for<0, nb>([&](auto jj) {
       constexpr int j = decltype(jj)::value;
-      float n_, o_;
-      point(std::integral_constant<int, b0 + j>{}, n_, o_);
-      const float si = S[j] * uim[b0 + j];
-      const float r1 = S1[j] * ure[b0 + j];
-      ax = fmaf(n_, si, ax);
-      ay = fmaf(o_, si, ay);
-      a11 = fmaf(n_ * n_, r1, a11);
-      a12 = fmaf(n_ * o_, r1, a12);
-      a22 = fmaf(o_ * o_, r1, a22);
+      constexpr int jp = b0 + j;
+      const float si = S[j] * uim[jp];
+      const float r1 = S1[j] * ure[jp];
+      if constexpr (jp < M && 2 * jp != W / 2) {
+        // omega = c + h/W, nu the lane's: the moments of si and r1 in c
+        constexpr float cm = (2 * jp < W / 2) ? (float)(2 * jp) * (1.f / W) : (float)(2 * jp - W) * (1.f / W);
+        m_si += si;
+        m_csi = fmaf(cm, si, m_csi);
+        m_r += r1;
+        m_cr = fmaf(cm, r1, m_cr);
+        m_ccr = fmaf(cm * cm, r1, m_ccr);
+      } else {
+        float n_, o_;
+        point(std::integral_constant<int, jp>{}, n_, o_);
+        ax = fmaf(n_, si, ax);
+        ay = fmaf(o_, si, ay);
+        a11 = fmaf(n_ * n_, r1, a11);
+        a12 = fmaf(n_ * o_, r1, a12);
+        a22 = fmaf(o_ * o_, r1, a22);
+      }
     });
     // Materialise the block's contribution here, so the compiler does not sink
     // the accumulation (and keep this block's sums alive) past later blocks.
     asm volatile("" : "+v"(ax), "+v"(ay), "+v"(a11), "+v"(a12), "+v"(a22));
+    asm volatile("" : "+v"(m_si), "+v"(m_csi), "+v"(m_r), "+v"(m_cr), "+v"(m_ccr));
   });
+  // the regular points' terms from their moments: with omega = c + h/W,
+  // sum nu si, sum omega si, sum nu^2 r1, sum nu omega r1, sum omega^2 r1
+  ax = fmaf(nu, m_si, ax);
+  ay += fmaf(hW, m_si, m_csi);
+  a11 = fmaf(nu * nu, m_r, a11);
+  a12 = fmaf(nu, fmaf(hW, m_r, m_cr), a12);
+  a22 += fmaf(hW, fmaf(hW, m_r, 2.f * m_cr), m_ccr);
   seg_sum5<W>(ax, ay, a11, a12, a22, s_x2);
   __syncthreads();
   // p_k = sum over the stamp's W partials, fixed order: LPK lanes per
