@@ -333,12 +333,11 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
   {
     // h(k_x) / W^2 with h = 1 on column 0 and 2 elsewhere, halved for the factor 2 in Gk
     const float colw = (c == 0 ? 0.5f : 1.f) / ((float)W * (float)W);
-    const float2 px = make_float2(cx, sx);
+    const float2 px = make_float2(cx * colw, sx * colw);  // the column's phase, with its weight
     static_for<0, M>([&](auto mm) {
       constexpr int m = decltype(mm)::value;
       const float2 P = p.psf_main[m * W + l];
-      const float2 gam = cscale(cmulc(P, Gk[m]), colw);   // P conj(G)
-      const float2 gp2 = cmul(gam, px);
+      const float2 gp2 = cmul(cmulc(P, Gk[m]), px);   // P conj(G) x phase x weight
       float2 u;
       if constexpr (2 * m == W / 2) {
         const float2 q0 = s_py[slot][W / 2 + h];
