@@ -339,27 +339,26 @@ render_small_kernel(RenderArgs p) {
       add_terms(lane_f(vk, k), wa);
     }
   } else {
-    {
-      const float v = var[0];
-      const float A = amp[0];
-      const float w = route_weight<W>(v * trB, p.flags);
-      if (w < 1.f && A != 0.f) {
-        rmask = 1u;
-        if (l == 0) s_rs[slot][0] = make_float2(v, (1.f - w) * A);
-      }
-      first_terms(v, w * A);
+    // Several stamps per wavefront: lane k of each stamp works out its
+    // stamp's component k (K <= W lanes), and the loop takes v and w A from
+    // it with a lane permute within the stamp's W lanes.
+    float vk = 0.f, wak = 0.f;
+    bool rk = false;
+    if (l < G.K) {
+      vk = var[l];
+      const float Ak = amp[l];
+      const float wk = route_weight<W>(vk * trB, p.flags);
+      wak = wk * Ak;
+      rk = wk < 1.f && Ak != 0.f;
+      if (rk) s_rs[slot][l] = make_float2(vk, (1.f - wk) * Ak);
     }
+    const unsigned long long rb = __ballot(rk);
+    rmask = (unsigned)(rb >> ((int)__lane_id() & ~(W - 1))) & (unsigned)((1ull << W) - 1ull);
+    first_terms(__shfl(vk, 0, W), __shfl(wak, 0, W));
     for (int k = 1; k < kloop; ++k) {
-      const float v = var[k];
-      const float A = (k < G.K) ? amp[k] : 0.f;
-      const float w = route_weight<W>(v * trB, p.flags);
-      if (w < 1.f && A != 0.f) {
-        rmask |= 1u << k;
-        if (l == 0) s_rs[slot][k] = make_float2(v, (1.f - w) * A);
-      }
-      const float wa = w * A;
+      const float wa = __shfl(wak, k, W);
       if (wa == 0.f) continue;
-      add_terms(v, wa);
+      add_terms(__shfl(vk, k, W), wa);
     }
   }
 
