@@ -145,15 +145,14 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
     }
   }
 
-  // routing: components with a real-space share (whatever their amplitude);
-  // with one stamp per workgroup, from the lanes' weights
+  // routing: components with a real-space share (whatever their amplitude),
+  // from the lanes' weights
   unsigned rmask = 0;
   if constexpr (C::SPB == 1) {
     rmask = (unsigned)__ballot(real_share) & ((1u << kKmax) - 1u);
-  } else {
-    for (int k = 0; k < kloop; ++k) {
-      if (k < G.K && route_weight<W>(var[k] * trB, p.flags) < 1.f) rmask |= 1u << k;
-    }
+  } else {  // this stamp's W lanes of the ballot
+    const unsigned long long rb = __ballot(real_share);
+    rmask = (unsigned)(rb >> ((int)__lane_id() & ~(W - 1))) & ((1u << kKmax) - 1u);
   }
 
   // ------------------------------------------------------------ load + real space
