@@ -60,6 +60,9 @@ render_small_kernel(RenderArgs p) {
   __shared__ float2 s_py[C::SPB][W + 2];
   __shared__ float2 s_nyq[C::SPB][W];
   __shared__ float2 s_rs[C::SPB][kKmax];  // (v, (1 - w) A) of the components with a real-space share
+  // per real-space component, its column constants (g, amplitude, -sxy / sxx,
+  // log2(e) / (2 sxx)) of the store below (not with the fused Lanczos shift)
+  __shared__ float4 s_rc[C::SPB][LZ ? 1 : kKmax];
   __shared__ float s_lw[C::SPB][12];      // raw Lanczos weights of the stamp (fused shift, W <= 64)
 
   const int l = (C::SPB == 1) ? (int)threadIdx.x : (int)threadIdx.x % W;
@@ -363,6 +366,23 @@ render_small_kernel(RenderArgs p) {
   }
 
   if constexpr (!kPsfFirst) psf_terms();
+  if constexpr (!LZ) {
+    // Lane k forms real-space component k's constants once per stamp; they
+    // do not depend on the lane's column.
+    if (l < kKmax && ((rmask >> l) & 1u)) {
+      const float2 rs = s_rs[slot][l];
+      const float v = rs.x, ra = rs.y;
+      const float sxx = fmaf(v, G.b11, pg[2]);
+      const float sxy = fmaf(v, G.b12, pg[3]);
+      const float syy = fmaf(v, G.b22, pg[4]);
+      const float det = fmaf(sxx, syy, -(sxy * sxy));
+      const float rdet = __builtin_amdgcn_rcpf(det);
+      const float rsxx = __builtin_amdgcn_rcpf(sxx);
+      s_rc[slot][l] = make_float4(__builtin_amdgcn_sqrtf(-kHalfLog2e * sxx * rdet),
+                                  ra * G.flux * pg[5] * kInv2Pi * __builtin_amdgcn_rsqf(det), -sxy * rsxx,
+                                  kHalfLog2e * rsxx);
+    }
+  }
 
   // Fractional-shift phases (shift theorem): exp(-2 pi i (fx nu + fy om)).
   // Every lane evaluates the y phase of row l and one x phase: lanes h = 0
@@ -593,14 +613,7 @@ render_small_kernel(RenderArgs p) {
       });
       if (rmask != 0) {
         for (unsigned mk = rmask; mk != 0; mk &= mk - 1) {
-          const float2 rs = s_rs[slot][__builtin_ctz(mk)];  // LDS, not global: no wait on the stores above
-          const float v = rs.x, ra = rs.y;
-          const float sxx = fmaf(v, G.b11, pg[2]);
-          const float sxy = fmaf(v, G.b12, pg[3]);
-          const float syy = fmaf(v, G.b22, pg[4]);
-          const float det = fmaf(sxx, syy, -(sxy * sxy));
-          const float rdet = __builtin_amdgcn_rcpf(det);
-          const float ampr = ra * G.flux * pg[5] * kInv2Pi * __builtin_amdgcn_rsqf(det);
+          const float4 rc = s_rc[slot][__builtin_ctz(mk)];  // LDS, not global: no wait on the stores above
           // Along this lane's column (dx fixed) the quadratic form is
           // dx^2 / sxx + (sxx / det) (dy - (sxy / sxx) dx)^2: the square is
           // completed about the conditional mean, so the exponent stays a
@@ -608,11 +621,10 @@ render_small_kernel(RenderArgs p) {
           // (an expansion about the tile's first row cancels terms of size
           // (W/2)^2 / syy there).  With dy = dyq + r the exponent is
           // k - u^2, u = g (r + m): two FMAs with an immediate r.
-          const float rsxx = __builtin_amdgcn_rcpf(sxx);
-          const float g = __builtin_amdgcn_sqrtf(-kHalfLog2e * sxx * rdet);
-          const float k0 = kHalfLog2e * dx * dx * rsxx;
+          const float g = rc.x, ampr = rc.y;
+          const float k0 = rc.w * dx * dx;
           const float dyq = (float)(q * C::HR) + dyc;
-          const float gm = g * fmaf(-sxy * rsxx, dx, dyq);
+          const float gm = g * fmaf(rc.z, dx, dyq);
           // two rows at a time, so that each exponential has an independent
           // instruction between it and its use
           static_for<0, C::HR / 2>([&](auto rr) {
