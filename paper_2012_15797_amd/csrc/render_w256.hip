@@ -159,11 +159,6 @@ __global__ void __launch_bounds__(w256::BLOCK) render_w256_kernel(RenderArgs pa)
     psfm = (GlobalF2)p.psf_main_tab[ps];
     psfn = (GlobalF2)p.psf_nyq_tab[ps];
   }
-  // The mixture tables are read-only during the launch: constant address
-  // space, so the uniform reads are scalar loads.
-  typedef const __attribute__((address_space(4))) float* ConstF;
-  ConstF amp = (ConstF)p.amp + G.table * kKmax;
-  ConstF var = (ConstF)p.var + G.table * kKmax;
   const float trB = G.b11 + G.b22;
   const float fs = G.flux * (1.f / ((float)W * (float)W));
 
@@ -252,28 +247,38 @@ __global__ void __launch_bounds__(w256::BLOCK) render_w256_kernel(RenderArgs pa)
   float S[M];
   float SN[3] = {0.f, 0.f, 0.f};
   static_for<0, M>([&](auto mm) { S[decltype(mm)::value] = 0.f; });
-  unsigned rmask = 0;
-  for (int k = 0; k < G.K; ++k) {
-    const float v = var[k];
-    const float A = amp[k];
-    const float w = route_weight<W>(v * trB, p.flags);
-    if (w < 1.f && A != 0.f) {
-      rmask |= 1u << k;
-      if (t == 0) {
+  // Lane k of every wavefront works out component k's route weight (K <= 16
+  // lanes), the loop takes v and w A from it by lane reads, and lane k of
+  // the first wavefront forms the component's real-space constants.
+  float vk = 0.f, wak = 0.f;
+  bool rk = false;
+  {
+    const int lk = lane;
+    if (lk < G.K) {
+      vk = p.var[G.table * kKmax + lk];
+      const float Ak = p.amp[G.table * kKmax + lk];
+      const float wk = route_weight<W>(vk * trB, p.flags);
+      wak = wk * Ak;
+      rk = wk < 1.f && Ak != 0.f;
+      if (rk && t == lk) {
         // the component convolved with the PSF Gaussian: covariance
         // v B + C_p, amplitude (1 - w) A flux a_p / (2 pi sqrt(det))
-        const float sxx = fmaf(v, G.b11, pg[2]);
-        const float sxy = fmaf(v, G.b12, pg[3]);
-        const float syy = fmaf(v, G.b22, pg[4]);
+        const float sxx = fmaf(vk, G.b11, pg[2]);
+        const float sxy = fmaf(vk, G.b12, pg[3]);
+        const float syy = fmaf(vk, G.b22, pg[4]);
         const float det = fmaf(sxx, syy, -(sxy * sxy));
         const float rsyy = __builtin_amdgcn_rcpf(syy);
-        s_rc[k] = make_float4((1.f - w) * A * G.flux * pg[5] * kInv2Pi * __builtin_amdgcn_rsqf(det),
-                              __builtin_amdgcn_sqrtf(-kHalfLog2e * syy * __builtin_amdgcn_rcpf(det)), sxy * rsyy,
-                              kHalfLog2e * rsyy);
+        s_rc[lk] = make_float4((1.f - wk) * Ak * G.flux * pg[5] * kInv2Pi * __builtin_amdgcn_rsqf(det),
+                               __builtin_amdgcn_sqrtf(-kHalfLog2e * syy * __builtin_amdgcn_rcpf(det)), sxy * rsyy,
+                               kHalfLog2e * rsyy);
       }
     }
-    const float wa = w * A;
+  }
+  const unsigned rmask = (unsigned)__ballot(rk) & ((1u << kKmax) - 1u);
+  for (int k = 0; k < G.K; ++k) {
+    const float wa = lane_f(wak, k);
     if (wa == 0.f) continue;
+    const float v = lane_f(vk, k);
     static_for<0, M / 8>([&](auto bb) {
       constexpr int b = decltype(bb)::value;
       if (v < vmax[b]) {
