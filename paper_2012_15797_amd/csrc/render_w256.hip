@@ -97,13 +97,67 @@ __device__ __forceinline__ uint32_t stamp_word(const RenderArgs& p, int64_t g, i
   return n ? (uint32_t)n[g] : 0u;
 }
 
+// A stamp's galaxy (Step 3) and the bound of its skip test, as 16 words in
+// LDS: the first wavefront forms them once and every wavefront reads them.
+constexpr int kGalWords = 16;
+
+// From the stamp's input words, word i held by lane i of the wavefront.
+template <int W>
+__device__ __forceinline__ void publish_galaxy(const RenderArgs& p, uint32_t word, int lane, uint32_t* s_gal) {
+  uint32_t w[7];
+  static_for<0, 7>([&](auto ii) {
+    constexpr int i = decltype(ii)::value;
+    w[i] = (uint32_t)__builtin_amdgcn_readlane((int)word, i);
+  });
+  const Galaxy G = make_galaxy<W>(p, GalaxyIn{__builtin_bit_cast(float, w[0]), __builtin_bit_cast(float, w[1]),
+                                              __builtin_bit_cast(float, w[2]), __builtin_bit_cast(float, w[3]),
+                                              __builtin_bit_cast(float, w[4]), __builtin_bit_cast(float, w[5]),
+                                              (int)w[6]});
+  const float lamq = -kQ * shape_min_eig(G);
+  if (lane == 0) {
+    uint4* d = reinterpret_cast<uint4*>(s_gal);
+    d[0] = make_uint4(__builtin_bit_cast(uint32_t, G.x0), __builtin_bit_cast(uint32_t, G.y0),
+                      __builtin_bit_cast(uint32_t, G.flux), __builtin_bit_cast(uint32_t, G.fx));
+    d[1] = make_uint4(__builtin_bit_cast(uint32_t, G.fy), (uint32_t)G.nx, (uint32_t)G.ny,
+                      __builtin_bit_cast(uint32_t, G.b11));
+    d[2] = make_uint4(__builtin_bit_cast(uint32_t, G.b12), __builtin_bit_cast(uint32_t, G.b22), (uint32_t)G.table,
+                      (uint32_t)G.K);
+    d[3] = make_uint4(G.ok ? 1u : 0u, __builtin_bit_cast(uint32_t, lamq), 0u, 0u);
+  }
+}
+
+// The published galaxy, in scalar registers.
+__device__ __forceinline__ Galaxy read_galaxy(const uint32_t* s_gal, float* lamq) {
+  const uint4* d = reinterpret_cast<const uint4*>(s_gal);
+  const uint4 a = d[0], b = d[1], c = d[2], e = d[3];
+  auto u = [](uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); };
+  auto f = [&](uint32_t v) { return __builtin_bit_cast(float, u(v)); };
+  Galaxy G;
+  G.x0 = f(a.x);
+  G.y0 = f(a.y);
+  G.flux = f(a.z);
+  G.fx = f(a.w);
+  G.fy = f(b.x);
+  G.nx = (int)u(b.y);
+  G.ny = (int)u(b.z);
+  G.b11 = f(b.w);
+  G.b12 = f(c.x);
+  G.b22 = f(c.y);
+  G.table = (int)u(c.z);
+  G.K = (int)u(c.w);
+  G.ok = u(e.x) != 0u;
+  *lamq = f(e.y);
+  return G;
+}
+
 // EIG: spatially varying PSF (eigen-PSF components with polynomial weights).
 // PT: each galaxy names its constant PSF in p.psf_id (serving batches).
 //
 // Persistent: the resident workgroups (one per CU: the LDS holds one half of
 // a stamp) take stamps in turn.  Lanes 0..9 of the first wavefront load the
 // inputs of a workgroup's next stamp while it renders the current one, so a
-// stamp starts without a memory round trip.
+// stamp starts without a memory round trip, and the first wavefront forms
+// the next stamp's galaxy for all sixteen.
 template <bool EIG, bool PT>
 __global__ void __launch_bounds__(w256::BLOCK) render_w256_kernel(RenderArgs pa) {
   using namespace w256;
@@ -118,8 +172,13 @@ __global__ void __launch_bounds__(w256::BLOCK) render_w256_kernel(RenderArgs pa)
   __shared__ float2 s_twc[8 * TWC];
   __shared__ float s_cj[kEigMax];   // eigen-PSF component weights at this galaxy's position
   __shared__ uint32_t s_in[kInWords];
+  __shared__ __attribute__((aligned(16))) uint32_t s_gal[kGalWords];
 
-  if (threadIdx.x < kInWords) s_in[threadIdx.x] = stamp_word<EIG, PT>(pa, blockIdx.x, threadIdx.x);
+  {
+    const uint32_t w0 = threadIdx.x < kInWords ? stamp_word<EIG, PT>(pa, blockIdx.x, threadIdx.x) : 0u;
+    if (threadIdx.x < kInWords) s_in[threadIdx.x] = w0;
+    if (threadIdx.x < 64) publish_galaxy<W>(pa, w0, (int)threadIdx.x, s_gal);
+  }
   if (threadIdx.x < 256) {
     const int hh = threadIdx.x >> 5, kg = threadIdx.x & 31;  // kg = 8 k + g
     s_twc[hh * TWC + kg] = twiddle_rt<+1, W>((kg & 7) * (8 * (kg >> 3) + hh));
@@ -134,15 +193,12 @@ __global__ void __launch_bounds__(w256::BLOCK) render_w256_kernel(RenderArgs pa)
   const int t = wv * 64 + lane;
   __syncthreads();  // s_in holds this stamp's inputs; the previous stamp is done with LDS
   uint32_t in[kInWords];
-  static_for<0, kInWords>([&](auto ii) {
+  static_for<7, kInWords>([&](auto ii) {  // the PSF id (PT) and the PSF position (EIG)
     constexpr int i = decltype(ii)::value;
     in[i] = __builtin_amdgcn_readfirstlane(s_in[i]);
   });
-  Galaxy G = make_galaxy<W>(p, GalaxyIn{__builtin_bit_cast(float, in[0]), __builtin_bit_cast(float, in[1]),
-                                        __builtin_bit_cast(float, in[2]), __builtin_bit_cast(float, in[3]),
-                                        __builtin_bit_cast(float, in[4]), __builtin_bit_cast(float, in[5]),
-                                        (int)in[6]});
-  make_uniform(G);
+  float lamq_pub;
+  Galaxy G = read_galaxy(s_gal, &lamq_pub);
   // PSF spectra are global memory (the pointer read from the PSF table would
   // otherwise be generic and its loads flat, which also count as LDS waits)
   GlobalF2 psfm = (GlobalF2)p.psf_main;
@@ -230,7 +286,7 @@ __global__ void __launch_bounds__(w256::BLOCK) render_w256_kernel(RenderArgs pa)
   // Skipping negligible bins: over block b of eight bins (k_y in
   // [64 b, 64 b + 63]) and this wavefront's columns, nu^2 + omega^2 >= r2[b],
   // so a component's exponent is at most -v lamq r2[b].
-  const float lamq = -kQ * uniform_f(shape_min_eig(G));
+  const float lamq = lamq_pub;
   int wvs = wv;  // renewed per stamp: the bounds below are not held across stamps
   asm volatile("" : "+s"(wvs));
   const float nlo = (float)(8 * wvs) * (1.f / W);
@@ -537,8 +593,10 @@ __global__ void __launch_bounds__(w256::BLOCK) render_w256_kernel(RenderArgs pa)
     });
   });
   if (!G.ok && t == 0) atomicAdd(p.invalid, 1ull);
-  // every thread read s_in at this stamp's start, before the barriers above
+  // every thread read s_in and s_gal at this stamp's start, before the
+  // barriers above
   if (t < kInWords) s_in[t] = in_next;
+  if (wv == 0) publish_galaxy<W>(p, in_next, lane, s_gal);
   }  // stamps of this workgroup
 }
 
