@@ -161,17 +161,25 @@ render_small_kernel(RenderArgs p) {
       qv[m] = fmaf(cm, fmaf(cm, g2, e1), e0);
     }
   });
-  qv[M] = fmaf(-0.5f, fmaf(g2, -0.5f, g1), g0);  // Nyquist row, omega = -1/2
-
   // Nyquist column k_x = W/2: lane l takes row k_y = l at nu = +1/2 and -1/2.
   // The corner's omega = -1/2 twins need no evaluation of their own: the
   // mixture transform is even, so (+-1/2, -1/2) equals (-+1/2, +1/2), the
-  // pair that lane W/2 (omega = +1/2) holds.
+  // pair that lane W/2 (omega = +1/2) holds.  Up to 64 x 64 the -1/2 values
+  // need no evaluation either: (-1/2, omega_l) equals (+1/2, -omega_l), lane
+  // W - l's, except at the corner, whose (-1/2, +1/2) the h = 1 lanes
+  // evaluate in slot M (where the h = 0 lanes hold the Nyquist row's
+  // omega = -1/2 twin and the h = 1 lanes would repeat it).
+  constexpr bool kMirrorN = W <= 64;
+  constexpr int NQ = kMirrorN ? 1 : 2;
   const float omN = (l < W / 2) ? (float)l * (1.f / W) : (l == W / 2 ? 0.5f : (float)(l - W) * (1.f / W));
   const float qa = kQ * G.b11 * 0.25f, qb = kQ * G.b12, qd = kQ * G.b22;
   float qn[2];
   qn[0] = fmaf(omN, fmaf(qd, omN, qb), qa);      // (+1/2, omN)
   qn[1] = fmaf(omN, fmaf(qd, omN, -qb), qa);     // (-1/2, omN)
+  qv[M] = fmaf(-0.5f, fmaf(g2, -0.5f, g1), g0);  // Nyquist row, omega = -1/2
+  if constexpr (kMirrorN) {
+    if (h) qv[M] = fmaf(0.5f, fmaf(qd, 0.5f, -qb), qa);  // the corner (-1/2, +1/2)
+  }
 
   // PSF spectrum of this lane's bins and the PSF Gaussian (step 2; for a
   // varying PSF, the weighted sum of the components at the galaxy's image
@@ -305,7 +313,7 @@ render_small_kernel(RenderArgs p) {
       constexpr int m = decltype(mm)::value;
       S[m] = wa * __builtin_amdgcn_exp2f(v * qv[m]);
     });
-    static_for<0, 2>([&](auto jj) {
+    static_for<0, NQ>([&](auto jj) {
       constexpr int j = decltype(jj)::value;
       SN[j] = wa * __builtin_amdgcn_exp2f(v * qn[j]);
     });
@@ -315,7 +323,7 @@ render_small_kernel(RenderArgs p) {
       constexpr int m = decltype(mm)::value;
       S[m] = fmaf(wa, __builtin_amdgcn_exp2f(v * qv[m]), S[m]);
     });
-    static_for<0, 2>([&](auto jj) {
+    static_for<0, NQ>([&](auto jj) {
       constexpr int j = decltype(jj)::value;
       SN[j] = fmaf(wa, __builtin_amdgcn_exp2f(v * qn[j]), SN[j]);
     });
@@ -366,6 +374,11 @@ render_small_kernel(RenderArgs p) {
   }
 
   if constexpr (!kPsfFirst) psf_terms();
+  if constexpr (kMirrorN) {
+    const float mirrored = __shfl(SN[0], (W - l) & (W - 1), W);
+    const float cornerv = __shfl(S[M], 1, W);  // lane 1 of the stamp: h = 1
+    SN[1] = (l == W / 2) ? cornerv : mirrored;
+  }
   if constexpr (!LZ) {
     // Lane k forms real-space component k's constants once per stamp; they
     // do not depend on the lane's column.
