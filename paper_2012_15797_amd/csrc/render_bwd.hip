@@ -44,9 +44,10 @@ struct BwdCfg {
   static constexpr int TNP = W < 32 ? TN + 16 : TN;
   static constexpr int CH = W <= 64 ? W : 32; // rows per load chunk
   static constexpr int NP = M + 3;            // evaluation points per lane
-  // points per block of the component loop: 35 points in blocks of 12, 12, 11 at 64, 67 in
-  // five of 12 and one of 7 at 128 (no spill at either; 18 spills at 64)
-  static constexpr int PB = M <= 16 ? NP : 12;
+  // points per block of the component loop: 35 points in blocks of 12, 12, 11 at 64 (blocks
+  // of 18 spill), 67 in blocks of 23, 22, 22 at 128 (in the accumulation registers there;
+  // one block of 67 spills to memory)
+  static constexpr int PB = M <= 16 ? NP : (W == 128 ? 23 : 12);
   static constexpr int WPE = W == 16 ? 3 : (W <= 64 ? 2 : 1);  // occupancy target (waves per SIMD)
 };
 
