@@ -405,14 +405,27 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
         point(std::integral_constant<int, jp>{}, n_, o_);
         gq[j] = kQ * fmaf(G.b11 * n_, n_, fmaf(2.f * G.b12 * n_, o_, G.b22 * o_ * o_));
       }
-      S[j] = 0.f;
-      S1[j] = 0.f;
     });
+    // Component 0 initialises the sums (every table has one).  With w = 0 it
+    // adds zeros to S and S1, and its p_k partial, finite since e <= 1, is
+    // only ever multiplied by w or by the ramp slope, both zero then.
+    {
+      const float4 cp = s_cmp[slot][0];
+      float pk = 0.f;
+      static_for<0, nb>([&](auto jj) {
+        constexpr int j = decltype(jj)::value;
+        const float e = __builtin_amdgcn_exp2f(cp.x * gq[j]);
+        S[j] = cp.y * e;
+        S1[j] = cp.z * e;
+        pk = fmaf(ure[b0 + j], e, pk);
+      });
+      s_pk[l] += pk;
+    }
     // The next component's constants and partial are read one iteration
     // ahead, so that the LDS latency falls behind this component's work.
-    float4 cpn = s_cmp[slot][0];
-    float pkn = s_pk[l];
-    for (int k = 0; k < kloop; ++k) {
+    float4 cpn = s_cmp[slot][1];
+    float pkn = s_pk[PKS + l];
+    for (int k = 1; k < kloop; ++k) {
       // p_k is needed when w_k > 0 (amplitude and ramp terms); w_k = 0 means n_k <= 3,
       // where the ramp slope vanishes too
       const float4 cp = cpn;
