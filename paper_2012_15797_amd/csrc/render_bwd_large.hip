@@ -339,10 +339,23 @@ render_bwd_w256_kernel(RenderArgs p, const float* __restrict__ gout, float* __re
       float n_, o_;
       point(std::integral_constant<int, b0 + j>{}, n_, o_);
       gq[j] = kQ * fmaf(G.b11 * n_, n_, fmaf(2.f * G.b12 * n_, o_, G.b22 * o_ * o_));
-      S[j] = 0.f;
-      S1[j] = 0.f;
     });
-    for (int k = 0; k < G.K; ++k) {
+    {  // component 0 initialises the sums (as in the W <= 128 adjoint)
+      const float v = var[0];
+      const float w = route_weight<W>(v * trB, p.flags);
+      const float wa = w * amp[0];
+      const float wav = wa * v;
+      float pk = 0.f;
+      static_for<0, nb>([&](auto jj) {
+        constexpr int j = decltype(jj)::value;
+        const float e = __builtin_amdgcn_exp2f(v * gq[j]);
+        S[j] = wa * e;
+        S1[j] = wav * e;
+        pk = fmaf(ure[b0 + j], e, pk);
+      });
+      s_pk[l] += pk;
+    }
+    for (int k = 1; k < G.K; ++k) {
       const float v = var[k];
       const float w = route_weight<W>(v * trB, p.flags);
       if (w == 0.f) continue;  // A_k = 0 still needs p_k for dL/dA_k
