@@ -22,7 +22,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2012_15797_amd", "csrc")
 INCLUDE = os.path.join(ROOT, "include")
-DRIVER = os.path.join(ROOT, "tests", "native", "sched_check.cpp")
+SCHED_MAIN = os.path.join(ROOT, "tests", "native", "sched_check.cpp")
 SOURCES = [os.path.join(CSRC, "sched.cpp"), os.path.join(CSRC, "gfc_error.cpp")]
 
 
@@ -36,7 +36,7 @@ def _clang():
 def _build_and_run(tmp_path, san, csrc=CSRC):
     exe = tmp_path / f"sched_check_{san.replace(',', '_')}"
     cmd = [_clang(), "-std=c++17", "-O1", "-g", f"-fsanitize={san}", "-fno-omit-frame-pointer",
-           "-fno-sanitize-recover=all", "-I", INCLUDE, "-I", csrc, DRIVER,
+           "-fno-sanitize-recover=all", "-I", INCLUDE, "-I", csrc, SCHED_MAIN,
            *[os.path.join(csrc, os.path.basename(s)) for s in SOURCES], "-o", str(exe), "-pthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
@@ -54,7 +54,7 @@ def test_scheduler_is_clean_under_sanitizers(tmp_path, san):
 
 
 def test_thread_sanitizer_sees_a_planted_race(tmp_path):
-    """Control: the same driver against a copy of the core whose poll()
+    """Control: the same check program against a copy of the core whose poll()
     reads the request table without the loop's lock."""
     src = tmp_path / "csrc"
     src.mkdir()
