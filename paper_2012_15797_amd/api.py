@@ -298,10 +298,13 @@ def gfc_backward_workspace_bytes(n: int) -> int:
 
 
 def gfc_render_stamps_backward(ctx, psf, mix, x, y, flux, r_e, e1, e2, W, grad_out, mix_id=None,
-                               flags=0, cd=None, grad_params=None, grad_amp=None, workspace=None, mix_amp=None):
+                               flags=0, cd=None, grad_params=None, grad_amp=None, workspace=None, mix_amp=None,
+                               amp_grad=True):
     """Adjoint (gfc_render_stamps_backward): returns (grad_params [n, 6] =
     dL/d(x, y, flux, log r_e, e1, e2), grad_amp [n_tables, 16] accumulated).
-    mix_amp: the per-call amplitude table of the forward render, if it had one."""
+    mix_amp: the per-call amplitude table of the forward render, if it had one.
+    amp_grad=False passes NULL for grad_amp (no amplitude gradient, so no
+    reduction launches) and returns None in its place."""
     dev = ctx.torch_device
     g, n, keep = _galaxies(dev, x, y, flux, r_e, e1, e2, mix_id, cd, mix_amp=mix_amp, n_tables=mix.n_tables)
     go = grad_out.to(dev, torch.float32).contiguous()
@@ -309,12 +312,14 @@ def gfc_render_stamps_backward(ctx, psf, mix, x, y, flux, r_e, e1, e2, W, grad_o
         raise ValueError("grad_out must hold n*W*W elements")
     if grad_params is None:
         grad_params = torch.empty((n, 6), dtype=torch.float32, device=dev)
-    if grad_amp is None:
+    if not amp_grad:
+        grad_amp = None
+    elif grad_amp is None:
         grad_amp = torch.zeros((mix.n_tables, GFC_KMAX), dtype=torch.float32, device=dev)
     ws = ctypes.c_void_p(workspace.data_ptr()) if workspace is not None else None
     call("gfc_render_stamps_backward", ctx.handle, psf.handle, mix.handle, ctypes.byref(g), int(n),
          int(W), int(flags), ctypes.c_void_p(go.data_ptr()), ctypes.c_void_p(grad_params.data_ptr()),
-         ctypes.c_void_p(grad_amp.data_ptr()), ws, _stream_ptr(ctx.device))
+         ctypes.c_void_p(grad_amp.data_ptr()) if grad_amp is not None else None, ws, _stream_ptr(ctx.device))
     del keep
     return grad_params, grad_amp
 

@@ -147,6 +147,10 @@ def test_backward_deterministic_and_accumulating(ctx):
     gfc.gfc_render_stamps_backward(*args, grad_amp=acc)
     torch.cuda.synchronize()
     assert torch.allclose(acc, 2 * ga1, rtol=1e-6, atol=0)
+    # grad_amp NULL: no amplitude reduction, the parameter gradients unchanged
+    gp3, ga3 = gfc.gfc_render_stamps_backward(*args, amp_grad=False)
+    torch.cuda.synchronize()
+    assert ga3 is None and torch.equal(gp3, gp1)
     psf.close(); mix.close()
 
 
