@@ -154,6 +154,29 @@ def test_backward_deterministic_and_accumulating(ctx):
     psf.close(); mix.close()
 
 
+@pytest.mark.parametrize("W", [16, 128, 256])
+def test_backward_without_amplitude_gradient(ctx, W):
+    """grad_amp NULL launches no amplitude reduction and leaves the parameter
+    gradients bit for bit as they are with it (the bench times the adjoint
+    kernel alone this way)."""
+    import torch
+    import paper_2012_15797_amd as gfc
+
+    rng = np.random.Generator(np.random.PCG64(650 + W))
+    cfg = wl.config2(10)
+    n = 37 if W < 128 else 9
+    gal = wl.draw_galaxies(rng, n, W, (np.arange(n) % 2).astype(np.int32), r_e_range=(0.4, W / 5.0))
+    g = torch.as_tensor(rng.standard_normal((n, W, W)).astype(np.float32)).cuda()
+    psf, mix = lib_objects(ctx, cfg)
+    args = (ctx, psf, mix, gal.x, gal.y, gal.flux, gal.r_e, gal.e1, gal.e2, W, g)
+    gp1, ga1 = gfc.gfc_render_stamps_backward(*args, mix_id=gal.mix_id)
+    gp2, ga2 = gfc.gfc_render_stamps_backward(*args, mix_id=gal.mix_id, amp_grad=False)
+    torch.cuda.synchronize()
+    assert ga2 is None and bool(torch.isfinite(ga1).all())
+    assert torch.equal(gp1, gp2)
+    psf.close(); mix.close()
+
+
 def test_autograd_function_matches_adjoint(ctx):
     """torch.autograd through RenderStamps gives the library adjoint, with the
     log r_e chain applied (dL/dr_e = dL/dlog r_e / r_e) and amplitude
