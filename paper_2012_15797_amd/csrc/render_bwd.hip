@@ -425,14 +425,16 @@ render_bwd_small_kernel(RenderArgs p, const float* __restrict__ gout, float* __r
     // ahead, so that the LDS latency falls behind this component's work.
     float4 cpn = s_cmp[slot][1];
     float pkn = s_pk[PKS + l];
+#pragma unroll 2
     for (int k = 1; k < kloop; ++k) {
       // p_k is needed when w_k > 0 (amplitude and ramp terms); w_k = 0 means n_k <= 3,
       // where the ramp slope vanishes too
       const float4 cp = cpn;
       const float pk_before = pkn;
-      if (k + 1 < kloop) {
-        cpn = s_cmp[slot][k + 1];
-        pkn = s_pk[(k + 1) * PKS + l];
+      {  // unconditional, clamped into the arrays (the last read is not used)
+        const int kn = min(k + 1, kKmax - 1);
+        cpn = s_cmp[slot][kn];
+        pkn = s_pk[kn * PKS + l];
       }
       const float v = cp.x, wa = cp.y, wav = cp.z;
       if (cp.w == 0.f) continue;
