@@ -60,6 +60,7 @@ render_bwd_w256_kernel(RenderArgs p, const float* __restrict__ gout, float* __re
   __shared__ float s_red[NWAVE];
   __shared__ float s_racc[kKmax][6];
   __shared__ float s_pkw[kKmax][NWAVE];
+  __shared__ float4 s_cmp[kKmax];  // per component: v, w A, w A v, w (zero past the table's K)
 
   const int l = threadIdx.x;
   const int64_t gidx = blockIdx.x;  // the launcher sizes each grid to its chunk
@@ -71,9 +72,26 @@ render_bwd_w256_kernel(RenderArgs p, const float* __restrict__ gout, float* __re
   float2* slab = scratch + (int64_t)blockIdx.x * SLAB;
   float2* gT = slab;  // un-rolled g as [n][y] pairs (g[y][2n], g[y][2n+1])
 
-  unsigned rmask = 0;
-  for (int k = 0; k < G.K; ++k)
-    if (route_weight<W>(var[k] * trB, p.flags) < 1.f) rmask |= 1u << k;  // whatever A_k (dL/dA_k needs it)
+  // Lane k of every wavefront works out component k's route weight once per
+  // stamp; the real-space mask is the ballot of w < 1 (whatever A_k: dL/dA_k
+  // needs it), and the first wavefront leaves the Fourier-loop constants in LDS.
+  unsigned rmask;
+  {
+    const int k = l & 63;
+    float vk = 0.f, wk = 0.f, ak = 0.f;
+    bool rs = false;
+    if (k < G.K) {
+      vk = var[k];
+      wk = route_weight<W>(vk * trB, p.flags);
+      ak = amp[k];
+      rs = wk < 1.f;
+    }
+    rmask = (unsigned)__ballot(rs) & ((1u << kKmax) - 1u);
+    if (l < kKmax) {
+      const float wa = wk * ak;
+      s_cmp[l] = make_float4(vk, wa, wa * vk, wk);
+    }
+  }
   if (l < kKmax * 6) (&s_racc[0][0])[l] = 0.f;
 
   // ------------------------------------------------------------ load + real space
@@ -341,10 +359,8 @@ render_bwd_w256_kernel(RenderArgs p, const float* __restrict__ gout, float* __re
       gq[j] = kQ * fmaf(G.b11 * n_, n_, fmaf(2.f * G.b12 * n_, o_, G.b22 * o_ * o_));
     });
     {  // component 0 initialises the sums (as in the W <= 128 adjoint)
-      const float v = var[0];
-      const float w = route_weight<W>(v * trB, p.flags);
-      const float wa = w * amp[0];
-      const float wav = wa * v;
+      const float4 cp = s_cmp[0];
+      const float v = cp.x, wa = cp.y, wav = cp.z;
       float pk = 0.f;
       static_for<0, nb>([&](auto jj) {
         constexpr int j = decltype(jj)::value;
@@ -356,11 +372,9 @@ render_bwd_w256_kernel(RenderArgs p, const float* __restrict__ gout, float* __re
       s_pk[l] += pk;
     }
     for (int k = 1; k < G.K; ++k) {
-      const float v = var[k];
-      const float w = route_weight<W>(v * trB, p.flags);
-      if (w == 0.f) continue;  // A_k = 0 still needs p_k for dL/dA_k
-      const float wa = w * amp[k];
-      const float wav = wa * v;
+      const float4 cp = s_cmp[k];
+      if (cp.w == 0.f) continue;  // A_k = 0 still needs p_k for dL/dA_k
+      const float v = cp.x, wa = cp.y, wav = cp.z;
       float pk = 0.f;
       static_for<0, nb>([&](auto jj) {
         constexpr int j = decltype(jj)::value;
