@@ -371,8 +371,13 @@ render_bwd_w256_kernel(RenderArgs p, const float* __restrict__ gout, float* __re
       });
       s_pk[l] += pk;
     }
+    // the next component's constants read one iteration ahead (clamped into
+    // the table; the last read is not used), two components per trip
+    float4 cpn = s_cmp[1];
+#pragma unroll 2
     for (int k = 1; k < G.K; ++k) {
-      const float4 cp = s_cmp[k];
+      const float4 cp = cpn;
+      cpn = s_cmp[min(k + 1, kKmax - 1)];
       if (cp.w == 0.f) continue;  // A_k = 0 still needs p_k for dL/dA_k
       const float v = cp.x, wa = cp.y, wav = cp.z;
       float pk = 0.f;
