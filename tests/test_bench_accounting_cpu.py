@@ -59,3 +59,21 @@ def test_workload_means_are_the_quoted_figures():
     cfg = wl.config5()
     per = bench.workload_flops(cfg["gal"], cfg["mix"], 64, adjoint=True) / len(cfg["gal"].x)
     assert abs(per - 358_008) < 1.0
+
+
+def test_traffic_record_is_used_only_for_the_sources_it_was_taken_from(tmp_path, monkeypatch):
+    import hashlib
+
+    src = tmp_path / "k.hip"
+    src.write_text("kernel source\n")
+    h = hashlib.sha256(src.read_bytes()).hexdigest()[:16]
+    rec = tmp_path / "traffic.txt"
+    rec.write_text(f"kernel: k\nsource_sha256_16: {h}\nsources: k.hip\n"
+                   "fetch_bytes_per_launch: 100\nwrite_bytes_per_launch: 2000\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(rec))
+    assert bench.measured_traffic() == 2100.0
+    src.write_text("kernel source, changed\n")
+    assert bench.measured_traffic() is None
+    src.unlink()
+    assert bench.measured_traffic() is None
