@@ -77,3 +77,12 @@ def test_traffic_record_is_used_only_for_the_sources_it_was_taken_from(tmp_path,
     assert bench.measured_traffic() is None
     src.unlink()
     assert bench.measured_traffic() is None
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    import subprocess
+
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2", "--steps", "1"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
